@@ -1,0 +1,195 @@
+"""Throughput of the IGR hot path on one MI355X.
+
+A step is one SSP-RK3 step of the whole path (three right-hand sides, each
+with its ghost fill, Sigma source, Jacobi sweeps and fused reconstruction +
+LLF flux + divergence + stage update, plus the FP64 CFL reduction) over the
+256^3 periodic box (rho = 1 + 0.2 * Gaussian-smoothed noise, solenoidal
+k^-2 velocity at rms Mach 1.5, p = 1, alpha = dx^2, 5 sweeps, CFL 0.5),
+with the state resident in HBM.
+
+Prints one JSON line: cell-updates/s (cells x steps / time), the roofline
+of the dominant kernel measured with HIP events on the solver's stream
+during the timed region, and the oracle's rate on a bounded sample of the
+same workload on the host cores.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2505_07392_amd", "csrc")
+
+
+def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int) -> float:
+    """Compulsory HBM bytes per interior cell for one launch of `kernel`."""
+    if kernel == "flux_rk":
+        # stage 1 reads U (5) + Sigma (1), writes 5; stages 2 and 3 also read Un (5)
+        return esize * (11 + 16 + 16) / 3.0
+    if kernel == "jacobi":
+        return 3 * esize + csize          # Sigma_in, rho, b read; Sigma_out written
+    if kernel == "source":
+        return 4 * esize + csize          # rho, m read; b written
+    if kernel == "dt":
+        return 5 * esize
+    raise KeyError(kernel)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed PMC summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, seconds_target: float = 15.0):
+    """The FP64 oracle on a 128^3 instance of the same workload recipe."""
+    import torch
+
+    from oracle import igr_ref as ref
+    from paper_2505_07392_amd import inputs
+
+    n = 128
+    ws = inputs.periodic_box(n=n, seed=w.seed)
+    U = torch.from_numpy(ws.U)
+    prob = ref.Problem(n, n, n, ws.dx, ws.dy, ws.dz, alpha=ws.alpha, faces=("periodic",) * 6, nsweeps=ws.nsweeps)
+    sig = torch.zeros((n, n, n), dtype=torch.float64)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        U, sig = ref.rk3_step(prob, U, sig, ref.compute_dt(prob, U, w.cfl))
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or steps >= 50:
+            break
+    return {"value": n ** 3 * steps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} RK3 steps of the FP64 oracle on the 128^3 periodic box (same recipe and "
+                      f"seed as the 256^3 workload), {el:.1f} s"}
+
+
+def run_form(w, precision, steps, warmup):
+    import torch
+
+    from paper_2505_07392_amd import igr
+
+    s = igr.Solver.from_workload(w, precision=precision)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    for _ in range(warmup):
+        s.step(U, sig, cfl=w.cfl, sync=False)
+    s.check()
+    torch.cuda.synchronize()
+    s.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(U, sig, cfl=w.cfl, sync=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.timing(False)
+    s.check()
+    kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
+    s.close()
+    return el, kt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--forms", default="f32,bf16", help="extra precision forms timed on the same workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
+              "design is described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2505_07392_amd import igr, inputs
+
+    torch.cuda.set_device(0)
+    print(f"[bench] generating the {args.n}^3 periodic box", file=sys.stderr, flush=True)
+    w = inputs.periodic_box(n=args.n, seed=0)
+    print(f"[bench] timing {args.precision}: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)
+    cells = w.cells
+    esize = {"f64": 8, "f32": 4, "bf16": 2}
+    csize = {"f64": 8, "f32": 4, "bf16": 4}
+
+    el, kt = run_form(w, args.precision, args.steps, args.warmup)
+    value = cells * args.steps / el
+    # dominant kernel by total time in the timed region
+    dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
+    ms, count = kt[dom]
+    avg_s = ms / count / 1e3
+    try:
+        abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps) * cells
+    except KeyError:
+        abytes = None
+    workload = f"periodic_box_{args.n}"
+    achieved = abytes / avg_s / 1e9 if abytes else None
+    traffic = load_traffic(dom, f"{workload}_{args.precision}")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                "avg_launch_ms": ms / count, "launches": count,
+                "algorithmic_bytes_per_launch": abytes}
+    kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1], "avg_ms": round(v[0] / v[1], 5)}
+               for k, v in kt.items() if v[1] > 0}
+
+    forms = {}
+    for f in [x for x in args.forms.split(",") if x and x != args.precision]:
+        print(f"[bench] timing {f}", file=sys.stderr, flush=True)
+        e2, _ = run_form(w, f, args.steps, args.warmup)
+        forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps}
+
+    line = {
+        "metric": "cell-updates/s per RK3 step (incl. Sigma Jacobi)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{workload} periodic box {args.n}^3, rms Mach 1.5, alpha=dx^2, "
+                               f"{w.nsweeps} Jacobi sweeps, CFL 0.5", "cells": cells,
+                   "sweeps": w.nsweeps, "precision": args.precision},
+        "roofline": roofline,
+        "kernels": kernels,
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

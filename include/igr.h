@@ -1,0 +1,192 @@
+/*
+ * igr.h -- C ABI of libigr, the MI355X (gfx950) implementation of the hot
+ * path of the information-geometric-regularisation (IGR) compressible Euler
+ * solver of "Simulating many-engine spacecraft: Exceeding 1 quadrillion
+ * degrees of freedom via information geometric regularization"
+ * (arXiv 2505.07392).
+ *
+ * The problem is the IGR-modified Euler system, eqs. (6)-(8) of the paper
+ * with the viscous stress set to zero, closed by the ideal-gas law, eq. (4),
+ * and the entropic-pressure equation, eq. (9):
+ *
+ *   alpha [tr((grad u)^2) + tr^2(grad u)] = Sigma/rho - alpha div(grad Sigma / rho)
+ *
+ * discretised as in the "Discretization" subsection and Algorithm 1 ("The
+ * algorithm"): fifth-order linear reconstruction of the conserved variables
+ * and of Sigma, local Lax-Friedrichs fluxes with p + Sigma, second-order
+ * central velocity gradients for the left side of eq. (9), a 7-point stencil
+ * for its operator solved by a fixed number of Jacobi sweeps warm-started
+ * from the previous Sigma, and third-order SSP Runge-Kutta in time.
+ *
+ * Data layout (every array argument)
+ * ----------------------------------
+ * Cell arrays are padded with G = 3 ghost layers on every side and stored
+ * x fastest: one field holds (nz+6)*(ny+6)*(nx+6) elements, element
+ * (i, j, k) of the interior (0 <= i < nx, ...) at offset
+ * ((k+3)*(ny+6) + (j+3))*(nx+6) + (i+3).  A state U is five consecutive
+ * fields (rho, rho*u, rho*v, rho*w, E); Sigma and scalar outputs are one
+ * field.  The element type follows the context precision: double
+ * (IGR_F64), float (IGR_F32) or uint16_t holding bfloat16
+ * (IGR_BF16_F32: bfloat16 storage, float arithmetic).
+ *
+ * Ownership and streams
+ * ---------------------
+ * All array pointers are device pointers owned by the caller; the library
+ * never frees them.  Interior cells are inputs/outputs as documented per
+ * call; ghost layers of U and Sigma are library-written scratch.  Internal
+ * scratch (two more states, a second Sigma, the Sigma source, reduction
+ * buffers, the error flag) is allocated by igr_init on the device current
+ * at that time and released by igr_finalize.  `stream` is a hipStream_t
+ * passed as void* (NULL = the default stream); all work is enqueued on it.
+ * Calls that return host values (dt, residual, sums) synchronise that
+ * stream.  A context may be used by one host thread at a time; calls on
+ * one context must not overlap.
+ *
+ * Errors
+ * ------
+ * Every call returns IGR_OK (0) or an error code; no C++ exception crosses
+ * the ABI.  igr_last_error() returns a thread-local message for the last
+ * failing call.  IGR_ENONFINITE reports a face or cell state with
+ * rho <= 0, p <= 0 or a non-finite value seen by a kernel since the last
+ * check; the arrays are left as computed.  Asynchronous calls (igr_step
+ * with dt_used == NULL) record such states in a device flag that the next
+ * synchronising call (or igr_check) reports.
+ */
+#ifndef IGR_H
+#define IGR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IGR_OK = 0,
+    IGR_EINVAL = 1,        /* bad argument: null pointer, size, gamma <= 1, alpha < 0, ... */
+    IGR_ENOMEM = 2,        /* device allocation failed */
+    IGR_EHIP = 3,          /* HIP runtime error (message in igr_last_error) */
+    IGR_ENONFINITE = 4,    /* rho <= 0, p <= 0 or NaN/Inf seen by a kernel */
+    IGR_EUNSUPPORTED = 5   /* valid but unimplemented option */
+};
+
+enum { IGR_BC_PERIODIC = 0, IGR_BC_EXTRAP = 1 };
+
+enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2 };
+
+/* Uniform rectilinear grid of nx*ny*nz interior cells with spacings dx, dy,
+ * dz (paper, "Example simulation result": rectilinear grid).  Each extent
+ * must be >= 1; ghost indices wrap modulo the extent on periodic axes. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+} igr_grid;
+
+/* Inflow disc on the x-min face (engines are modelled by inflow boundary
+ * conditions: paper, "Example simulation result").  Centre (yc, zc),
+ * radius r and edge width `width` in physical units; primitive jet state
+ * (rho, ux, uy, uz, p).  Each x-min ghost column takes the disc whose
+ * centre is nearest to the column's cell centre ((j+1/2)dy, (k+1/2)dz)
+ * (lowest index on ties) and sets all three ghost layers to
+ * chi*U_jet + (1-chi)*U_extrap, chi = (1 - tanh((s - r)/width))/2 at
+ * distance s (chi = [s <= r] when width == 0), U_extrap being the first
+ * interior cell of that column. */
+typedef struct {
+    double yc, zc, r, width;
+    double rho, ux, uy, uz, p;
+} igr_patch;
+
+/* Boundary description: face kinds in the order -x, +x, -y, +y, -z, +z
+ * (IGR_BC_PERIODIC must come in pairs; IGR_BC_EXTRAP copies the first
+ * interior cell into all three ghost layers), plus optional inflow discs
+ * (require a non-periodic x axis).  Sigma uses periodic wrap on periodic
+ * faces and zero gradient on every other face.  The patch array is copied
+ * by igr_init. */
+typedef struct {
+    int32_t face[6];
+    int32_t npatch;
+    const igr_patch *patch;
+} igr_bc;
+
+/* Options: storage/arithmetic precision, reconstruction order (5), Jacobi
+ * sweeps per right-hand side (the paper uses up to 5: "Shock treatment with
+ * information geometric regularization"), flags (0). */
+typedef struct {
+    int32_t precision;
+    int32_t order;
+    int32_t nsweeps;
+    int32_t flags;
+} igr_opts;
+
+typedef struct igr_ctx igr_ctx;
+
+/* Create a context for one grid on the current device.  gamma > 1,
+ * alpha >= 0 (the paper takes alpha proportional to dx^2).  On success
+ * *out owns the scratch memory; release it with igr_finalize. */
+int igr_init(const igr_grid *grid, double gamma, double alpha, const igr_bc *bc,
+             const igr_opts *opts, igr_ctx **out);
+
+/* Release a context and its scratch (NULL is accepted). */
+int igr_finalize(igr_ctx *ctx);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *igr_last_error(void);
+
+/* Elements per padded field, (nz+6)*(ny+6)*(nx+6), and bytes per element. */
+int igr_field_size(const igr_ctx *ctx, int64_t *elems, int32_t *elem_bytes);
+
+/* Replace the primitive state (rho, ux, uy, uz, p) of inflow disc `index`
+ * (geometry unchanged).  Takes effect for later calls. */
+int igr_set_patch_state(igr_ctx *ctx, int32_t index, const double prim[5]);
+
+/* Entropic pressure: fill U's ghosts, form the source
+ * b = alpha [tr((grad u)^2) + tr^2(grad u)] with central differences, and
+ * run `nsweeps` Jacobi sweeps of eq. (9)'s 7-point discretisation
+ * (face coefficient (1/rho_c + 1/rho_nb)/2) starting from sigma's interior
+ * (warm start; paper: "Discretization" and "Shock treatment ...").
+ * On return sigma's interior holds the last iterate and its ghosts are
+ * filled.  If resid_l2 is not NULL it receives the FP64 l2 norm (no volume
+ * weight) of b - A sigma over interior cells (synchronises). */
+int igr_sigma_solve(igr_ctx *ctx, void *U, void *sigma, int32_t nsweeps, double *resid_l2,
+                    void *stream);
+
+/* One right-hand-side evaluation L(U) (Algorithm 1): ghosts, Sigma solve
+ * with the context's sweep count warm-started from sigma (in: previous
+ * Sigma, out: new Sigma), reconstruction, local Lax-Friedrichs fluxes
+ * with p + Sigma, divergence.  rhs's interior receives L(U); its ghosts
+ * are not written. */
+int igr_rhs(igr_ctx *ctx, void *U, void *sigma, void *rhs, void *stream);
+
+/* One SSP-RK3 step (Gottlieb & Shu; paper "Discretization") in place on U
+ * and sigma, one Sigma solve per stage warm-started from the previous
+ * stage.  dt = dt_fixed if dt_fixed > 0, else
+ * cfl / max_cells sum_d (|u_d| + c)/dx_d computed on the device in FP64.
+ * If dt_used is not NULL the stream is synchronised, *dt_used receives dt
+ * and the error flag is checked. */
+int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, double *dt_used,
+             void *stream);
+
+/* FP64 CFL time step of state U (rule as in igr_step; synchronises). */
+int igr_compute_dt(igr_ctx *ctx, const void *U, double cfl, double *dt, void *stream);
+
+/* FP64 totals sum_cells U dV of the five conserved variables in a fixed
+ * reduction order (synchronises). */
+int igr_sums(igr_ctx *ctx, const void *U, double out[5], void *stream);
+
+/* Synchronise the stream and report (and clear) the non-finite flag. */
+int igr_check(igr_ctx *ctx, void *stream);
+
+/* Per-kernel timing with HIP events on the call's stream (for measurement
+ * only).  igr_timing(ctx, 1) starts recording every launch; 0 stops.
+ * igr_kernel_time(ctx, name, &ms, &count) returns the summed duration in
+ * milliseconds and the launch count of kernel `name` since recording
+ * started (synchronises; names are listed by igr_kernel_name). */
+int igr_timing(igr_ctx *ctx, int32_t enable);
+int igr_kernel_time(igr_ctx *ctx, const char *name, double *ms, int64_t *count);
+const char *igr_kernel_name(int32_t index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGR_H */

@@ -1,0 +1,573 @@
+// libigr host runtime: context, scratch, boundary tables, launch sequences
+// and the C ABI declared in include/igr.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "igr.h"
+#include "igr_kernels.h"
+
+using namespace igr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define IGR_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? IGR_ENOMEM : IGR_EHIP,                         \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+#define IGR_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != IGR_OK) return rc_; \
+    } while (0)
+
+enum KernelId { K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source", "jacobi",
+                                           "flux_rk",  "dt",       "sums",   "resid"};
+
+struct TimingRecord {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct igr_ctx {
+    Geom g{};
+    int nx = 0, ny = 0, nz = 0;
+    double dx = 0, dy = 0, dz = 0;
+    int precision = IGR_F64;
+    int nsweeps = 5;
+    int faces[6] = {0, 0, 0, 0, 0, 0};
+    int device = 0;
+    size_t esize = 8;     // storage bytes per element
+    size_t csize = 8;     // arithmetic bytes per element (source array)
+    std::vector<igr_patch> patches;
+    int* d_owner = nullptr;
+    double* d_chi = nullptr;
+    double* d_jet = nullptr;
+    void* d_Ua = nullptr;
+    void* d_Ub = nullptr;
+    void* d_sig2 = nullptr;
+    void* d_b = nullptr;
+    double* d_partial = nullptr;
+    double* d_scalars = nullptr;  // [0] dt, [1..5] sums, [6] residual
+    int* d_flag = nullptr;
+    bool timing = false;
+    std::vector<TimingRecord> records;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[K_COUNT] = {};
+    long long kernel_count[K_COUNT] = {};
+};
+
+namespace {
+
+size_t field_bytes(const igr_ctx* c, size_t elem) { return (size_t)c->g.fs * elem; }
+
+hipEvent_t pooled_event(igr_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch helper: records start/stop events around the launch when timing.
+template <class F>
+int launch(igr_ctx* c, int kernel, hipStream_t s, F&& fn) {
+    TimingRecord rec{kernel, nullptr, nullptr};
+    if (c->timing) {
+        rec.start = pooled_event(c);
+        rec.stop = pooled_event(c);
+        if (rec.start) hipEventRecord(rec.start, s);
+    }
+    fn();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(IGR_EHIP, std::string("launch of ") + kKernelNames[kernel] + ": " + hipGetErrorString(e));
+    if (c->timing && rec.start && rec.stop) {
+        hipEventRecord(rec.stop, s);
+        c->records.push_back(rec);
+    }
+    return IGR_OK;
+}
+
+int collect_timing(igr_ctx* c) {
+    for (auto& r : c->records) {
+        IGR_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.f;
+        IGR_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        c->kernel_ms[r.kernel] += ms;
+        c->kernel_count[r.kernel] += 1;
+        c->event_pool.push_back(r.start);
+        c->event_pool.push_back(r.stop);
+    }
+    c->records.clear();
+    return IGR_OK;
+}
+
+dim3 cell_block() { return dim3(64, 4, 1); }
+dim3 cell_grid(const Geom& g) { return dim3((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]); }
+
+template <class T>
+int fill_state_ghosts(igr_ctx* c, T* U, hipStream_t s) {
+    for (int axis = 0; axis < 3; ++axis) {
+        const int a = axis == 0 ? 1 : 0;
+        const int b = axis == 2 ? 1 : 2;
+        const long long tot = 2LL * c->g.n[a] * c->g.n[b];
+        const int blocks = int((tot + 255) / 256);
+        const bool inflow = axis == 0 && !c->patches.empty();
+        IGR_TRY(launch(c, K_BC_STATE, s, [&] {
+            k_bc_state<T><<<blocks, 256, 0, s>>>(U, c->g, axis, inflow ? c->d_owner : nullptr, c->d_chi, c->d_jet);
+        }));
+    }
+    return IGR_OK;
+}
+
+template <class T>
+int fill_sigma_ghosts(igr_ctx* c, T* Sg, hipStream_t s) {
+    for (int axis = 0; axis < 3; ++axis) {
+        const int a = axis == 0 ? 1 : 0;
+        const int b = axis == 2 ? 1 : 2;
+        const long long tot = 2LL * c->g.n[a] * c->g.n[b];
+        const int blocks = int((tot + 255) / 256);
+        IGR_TRY(launch(c, K_BC_SIGMA, s, [&] { k_bc_sigma<T><<<blocks, 256, 0, s>>>(Sg, c->g, axis); }));
+    }
+    return IGR_OK;
+}
+
+// Source + nsweeps Jacobi sweeps from `sig` (warm start).  U ghosts must be
+// filled.  The last iterate ends in `sig` (a device copy follows an odd
+// number of sweeps); its ghosts are then filled.
+template <class T>
+int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
+    using C = typename Storage<T>::C;
+    C* b = static_cast<C*>(c->d_b);
+    IGR_TRY(launch(c, K_SOURCE, s, [&] { k_source<T, C><<<cell_grid(c->g), cell_block(), 0, s>>>(U, b, c->g); }));
+    T* src = sig;
+    T* dst = static_cast<T*>(c->d_sig2);
+    for (int it = 0; it < nsweeps; ++it) {
+        IGR_TRY(launch(c, K_JACOBI, s, [&] {
+            k_jacobi<T, C><<<cell_grid(c->g), cell_block(), 0, s>>>(src, dst, b, U, c->g);
+        }));
+        T* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    if (src != sig) IGR_HIP(hipMemcpyAsync(sig, src, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
+    return fill_sigma_ghosts(c, sig, s);
+}
+
+template <class T, int MODE>
+int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
+              hipStream_t s) {
+    return launch(c, K_FLUX, s, [&] {
+        k_flux<T, MODE><<<cell_grid(c->g), cell_block(), 0, s>>>(U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag);
+    });
+}
+
+template <class T>
+int speed_dt_impl(igr_ctx* c, const T* U, double cfl, hipStream_t s) {
+    IGR_TRY(launch(c, K_DT, s, [&] {
+        k_speed_partial<T><<<RED_BLOCKS, RED_THREADS, 0, s>>>(U, c->g, c->d_partial, c->d_flag);
+        k_dt_final<<<1, RED_THREADS, 0, s>>>(c->d_partial, RED_BLOCKS, cfl, c->d_scalars);
+    }));
+    return IGR_OK;
+}
+
+int read_flag(igr_ctx* c, hipStream_t s) {
+    int flag = 0;
+    IGR_HIP(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    if (flag) {
+        IGR_HIP(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+        IGR_HIP(hipStreamSynchronize(s));
+        return fail(IGR_ENONFINITE, "a kernel saw rho <= 0, p <= 0 or a non-finite value");
+    }
+    return IGR_OK;
+}
+
+template <class T>
+int rhs_impl(igr_ctx* c, T* U, T* sig, T* rhs, hipStream_t s) {
+    IGR_TRY(fill_state_ghosts(c, U, s));
+    IGR_TRY(sigma_solve_impl(c, U, sig, c->nsweeps, s));
+    return flux_impl<T, MODE_RHS>(c, U, sig, nullptr, rhs, nullptr, 0.0, s);
+}
+
+template <class T>
+int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t s) {
+    const double* dtp = nullptr;
+    if (!(dt_fixed > 0.0)) {
+        IGR_TRY(speed_dt_impl(c, U, cfl, s));
+        dtp = c->d_scalars;
+    }
+    T* Ua = static_cast<T*>(c->d_Ua);
+    T* Ub = static_cast<T*>(c->d_Ub);
+    // stage 1: U1 = Un + dt L(Un)
+    IGR_TRY(fill_state_ghosts(c, U, s));
+    IGR_TRY(sigma_solve_impl(c, U, sig, c->nsweeps, s));
+    IGR_TRY((flux_impl<T, MODE_STAGE1>(c, U, sig, nullptr, Ua, dtp, dt_fixed, s)));
+    // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
+    IGR_TRY(fill_state_ghosts(c, Ua, s));
+    IGR_TRY(sigma_solve_impl(c, Ua, sig, c->nsweeps, s));
+    IGR_TRY((flux_impl<T, MODE_STAGE2>(c, Ua, sig, U, Ub, dtp, dt_fixed, s)));
+    // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un
+    IGR_TRY(fill_state_ghosts(c, Ub, s));
+    IGR_TRY(sigma_solve_impl(c, Ub, sig, c->nsweeps, s));
+    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, sig, U, U, dtp, dt_fixed, s)));
+    return IGR_OK;
+}
+
+template <class T>
+int sums_impl(igr_ctx* c, const T* U, double out[5], hipStream_t s) {
+    IGR_TRY(launch(c, K_SUMS, s, [&] {
+        k_sums_partial<T><<<RED_BLOCKS, RED_THREADS, 0, s>>>(U, c->g, c->d_partial);
+        k_sum_final<5><<<1, RED_THREADS, 0, s>>>(c->d_partial, RED_BLOCKS, c->dx * c->dy * c->dz, c->d_scalars + 1);
+    }));
+    IGR_HIP(hipMemcpyAsync(out, c->d_scalars + 1, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    return IGR_OK;
+}
+
+template <class T>
+int resid_impl(igr_ctx* c, const T* U, const T* sig, double* out, hipStream_t s) {
+    using C = typename Storage<T>::C;
+    const C* b = static_cast<const C*>(c->d_b);
+    IGR_TRY(launch(c, K_RESID, s, [&] {
+        k_resid_partial<T, C><<<RED_BLOCKS, RED_THREADS, 0, s>>>(sig, b, U, c->g, c->d_partial);
+        k_sum_final<1><<<1, RED_THREADS, 0, s>>>(c->d_partial, RED_BLOCKS, 1.0, c->d_scalars + 6);
+    }));
+    double r2 = 0.0;
+    IGR_HIP(hipMemcpyAsync(&r2, c->d_scalars + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    *out = std::sqrt(r2);
+    return IGR_OK;
+}
+
+// Per-column owner/chi of the x-min inflow discs (host, FP64).
+int upload_patches(igr_ctx* c) {
+    const int ny = c->ny, nz = c->nz;
+    std::vector<int> owner((size_t)ny * nz, -1);
+    std::vector<double> chi((size_t)ny * nz, 0.0);
+    for (int k = 0; k < nz; ++k) {
+        for (int j = 0; j < ny; ++j) {
+            const double y = (j + 0.5) * c->dy, z = (k + 0.5) * c->dz;
+            double best = INFINITY;
+            int q = -1;
+            for (size_t p = 0; p < c->patches.size(); ++p) {
+                const double ey = y - c->patches[p].yc, ez = z - c->patches[p].zc;
+                const double d2 = ey * ey + ez * ez;
+                if (d2 < best) {
+                    best = d2;
+                    q = int(p);
+                }
+            }
+            owner[(size_t)k * ny + j] = q;
+            if (q >= 0) {
+                const igr_patch& pa = c->patches[q];
+                chi[(size_t)k * ny + j] = pa.width > 0 ? 0.5 * (1.0 - std::tanh((std::sqrt(best) - pa.r) / pa.width))
+                                                       : (best <= pa.r * pa.r ? 1.0 : 0.0);
+            }
+        }
+    }
+    IGR_HIP(hipMemcpy(c->d_owner, owner.data(), owner.size() * sizeof(int), hipMemcpyHostToDevice));
+    IGR_HIP(hipMemcpy(c->d_chi, chi.data(), chi.size() * sizeof(double), hipMemcpyHostToDevice));
+    return IGR_OK;
+}
+
+int upload_jets(igr_ctx* c, hipStream_t s, bool sync) {
+    if (c->patches.empty()) return IGR_OK;
+    std::vector<double> jet(c->patches.size() * 5);
+    const double gm = c->g.gamma;
+    for (size_t p = 0; p < c->patches.size(); ++p) {
+        const igr_patch& pa = c->patches[p];
+        jet[p * 5 + 0] = pa.rho;
+        jet[p * 5 + 1] = pa.rho * pa.ux;
+        jet[p * 5 + 2] = pa.rho * pa.uy;
+        jet[p * 5 + 3] = pa.rho * pa.uz;
+        jet[p * 5 + 4] = pa.p / (gm - 1.0) + 0.5 * pa.rho * (pa.ux * pa.ux + pa.uy * pa.uy + pa.uz * pa.uz);
+    }
+    IGR_HIP(hipMemcpyAsync(c->d_jet, jet.data(), jet.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (sync) IGR_HIP(hipStreamSynchronize(s));
+    return IGR_OK;
+}
+
+void release(igr_ctx* c) {
+    if (!c) return;
+    void* ptrs[] = {c->d_owner, c->d_chi, c->d_jet, c->d_Ua, c->d_Ub, c->d_sig2, c->d_b, c->d_partial, c->d_scalars, c->d_flag};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& r : c->records) {
+        c->event_pool.push_back(r.start);
+        c->event_pool.push_back(r.stop);
+    }
+    for (hipEvent_t e : c->event_pool)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+#define DISPATCH(ctx, FN, ...)                                                                        \
+    ((ctx)->precision == IGR_F64   ? FN<double>(__VA_ARGS__)                                          \
+     : (ctx)->precision == IGR_F32 ? FN<float>(__VA_ARGS__)                                           \
+                                   : FN<bf16>(__VA_ARGS__))
+
+template <class T>
+int rhs_t(igr_ctx* c, void* U, void* sig, void* rhs, hipStream_t s) {
+    return rhs_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), static_cast<T*>(rhs), s);
+}
+template <class T>
+int step_t(igr_ctx* c, void* U, void* sig, double cfl, double dt_fixed, hipStream_t s) {
+    return step_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), cfl, dt_fixed, s);
+}
+template <class T>
+int sigma_t(igr_ctx* c, void* U, void* sig, int nsweeps, double* resid, hipStream_t s) {
+    IGR_TRY(fill_state_ghosts(c, static_cast<T*>(U), s));
+    IGR_TRY(sigma_solve_impl(c, static_cast<T*>(U), static_cast<T*>(sig), nsweeps, s));
+    if (resid) {
+        // the source of the final U is still in d_b
+        IGR_TRY(resid_impl(c, static_cast<const T*>(U), static_cast<const T*>(sig), resid, s));
+    }
+    return IGR_OK;
+}
+template <class T>
+int dt_t(igr_ctx* c, const void* U, double cfl, hipStream_t s) {
+    return speed_dt_impl(c, static_cast<const T*>(U), cfl, s);
+}
+template <class T>
+int sums_t(igr_ctx* c, const void* U, double* out, hipStream_t s) {
+    return sums_impl(c, static_cast<const T*>(U), out, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* igr_last_error(void) { return g_last_error.c_str(); }
+
+const char* igr_kernel_name(int32_t index) {
+    if (index < 0 || index >= K_COUNT) return nullptr;
+    return kKernelNames[index];
+}
+
+int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc, const igr_opts* opts,
+             igr_ctx** out) {
+    if (!grid || !bc || !opts || !out) return fail(IGR_EINVAL, "null argument");
+    *out = nullptr;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(IGR_EINVAL, "grid extents must be >= 1");
+    if (!(grid->dx > 0) || !(grid->dy > 0) || !(grid->dz > 0)) return fail(IGR_EINVAL, "spacings must be > 0");
+    if (!(gamma > 1.0)) return fail(IGR_EINVAL, "gamma must be > 1");
+    if (!(alpha >= 0.0)) return fail(IGR_EINVAL, "alpha must be >= 0");
+    for (int f = 0; f < 6; ++f)
+        if (bc->face[f] != IGR_BC_PERIODIC && bc->face[f] != IGR_BC_EXTRAP) return fail(IGR_EINVAL, "unknown face kind");
+    for (int d = 0; d < 3; ++d)
+        if ((bc->face[2 * d] == IGR_BC_PERIODIC) != (bc->face[2 * d + 1] == IGR_BC_PERIODIC))
+            return fail(IGR_EINVAL, "periodic faces must come in pairs");
+    if (bc->npatch < 0 || (bc->npatch > 0 && !bc->patch)) return fail(IGR_EINVAL, "bad patch list");
+    if (bc->npatch > 0 && bc->face[0] == IGR_BC_PERIODIC) return fail(IGR_EINVAL, "inflow discs need a non-periodic x axis");
+    for (int p = 0; p < bc->npatch; ++p) {
+        const igr_patch& pa = bc->patch[p];
+        if (!(pa.r >= 0) || !(pa.width >= 0) || !(pa.rho > 0) || !(pa.p > 0))
+            return fail(IGR_EINVAL, "inflow disc needs r >= 0, width >= 0, rho > 0, p > 0");
+    }
+    if (opts->precision != IGR_F64 && opts->precision != IGR_F32 && opts->precision != IGR_BF16_F32)
+        return fail(IGR_EINVAL, "unknown precision");
+    if (opts->order != 5) return fail(IGR_EUNSUPPORTED, "only fifth-order reconstruction is implemented");
+    if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
+    if (opts->flags != 0) return fail(IGR_EUNSUPPORTED, "flags must be 0");
+
+    igr_ctx* c = new (std::nothrow) igr_ctx();
+    if (!c) return fail(IGR_ENOMEM, "host allocation failed");
+    c->nx = grid->nx;
+    c->ny = grid->ny;
+    c->nz = grid->nz;
+    c->dx = grid->dx;
+    c->dy = grid->dy;
+    c->dz = grid->dz;
+    c->precision = opts->precision;
+    c->nsweeps = opts->nsweeps;
+    for (int f = 0; f < 6; ++f) c->faces[f] = bc->face[f];
+    c->patches.assign(bc->patch, bc->patch + bc->npatch);
+    const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;
+    Geom& g = c->g;
+    g.n[0] = grid->nx;
+    g.n[1] = grid->ny;
+    g.n[2] = grid->nz;
+    if (px * py > 0x7fffffffLL) {
+        delete c;
+        return fail(IGR_EINVAL, "x-y plane too large");
+    }
+    g.st[0] = 1;
+    g.st[1] = int(px);
+    g.st[2] = int(px * py);
+    g.fs = px * py * pz;
+    g.ih[0] = 1.0 / grid->dx;
+    g.ih[1] = 1.0 / grid->dy;
+    g.ih[2] = 1.0 / grid->dz;
+    g.gamma = gamma;
+    g.alpha = alpha;
+    for (int d = 0; d < 3; ++d) g.periodic[d] = bc->face[2 * d] == IGR_BC_PERIODIC;
+    c->esize = c->precision == IGR_F64 ? 8 : c->precision == IGR_F32 ? 4 : 2;
+    c->csize = c->precision == IGR_F64 ? 8 : 4;
+
+    auto alloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? IGR_ENOMEM : IGR_EHIP,
+                                         std::string("hipMalloc: ") + hipGetErrorString(e));
+        return IGR_OK;
+    };
+    int rc = IGR_OK;
+    if (hipGetDevice(&c->device) != hipSuccess) rc = fail(IGR_EHIP, "hipGetDevice failed");
+    if (!rc) rc = alloc(&c->d_Ua, 5 * field_bytes(c, c->esize));
+    if (!rc) rc = alloc(&c->d_Ub, 5 * field_bytes(c, c->esize));
+    if (!rc) rc = alloc(&c->d_sig2, field_bytes(c, c->esize));
+    if (!rc) rc = alloc(&c->d_b, field_bytes(c, c->csize));
+    if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));
+    if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
+    if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
+    if (!rc && !c->patches.empty()) {
+        const size_t cols = (size_t)c->ny * c->nz;
+        rc = alloc((void**)&c->d_owner, cols * sizeof(int));
+        if (!rc) rc = alloc((void**)&c->d_chi, cols * sizeof(double));
+        if (!rc) rc = alloc((void**)&c->d_jet, c->patches.size() * 5 * sizeof(double));
+        if (!rc) rc = upload_patches(c);
+        if (!rc) rc = upload_jets(c, nullptr, true);
+    }
+    if (!rc) {
+        // scratch starts defined: zero states, Sigma copy and source
+        if (hipMemset(c->d_Ua, 0, 5 * field_bytes(c, c->esize)) != hipSuccess ||
+            hipMemset(c->d_Ub, 0, 5 * field_bytes(c, c->esize)) != hipSuccess ||
+            hipMemset(c->d_sig2, 0, field_bytes(c, c->esize)) != hipSuccess ||
+            hipMemset(c->d_b, 0, field_bytes(c, c->csize)) != hipSuccess ||
+            hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            rc = fail(IGR_EHIP, "scratch initialisation failed");
+    }
+    if (rc) {
+        release(c);
+        return rc;
+    }
+    *out = c;
+    return IGR_OK;
+}
+
+int igr_finalize(igr_ctx* ctx) {
+    if (!ctx) return IGR_OK;
+    hipDeviceSynchronize();
+    release(ctx);
+    return IGR_OK;
+}
+
+int igr_field_size(const igr_ctx* ctx, int64_t* elems, int32_t* elem_bytes) {
+    if (!ctx) return fail(IGR_EINVAL, "null context");
+    if (elems) *elems = ctx->g.fs;
+    if (elem_bytes) *elem_bytes = int32_t(ctx->esize);
+    return IGR_OK;
+}
+
+int igr_set_patch_state(igr_ctx* ctx, int32_t index, const double prim[5]) {
+    if (!ctx || !prim) return fail(IGR_EINVAL, "null argument");
+    if (index < 0 || index >= (int)ctx->patches.size()) return fail(IGR_EINVAL, "patch index out of range");
+    if (!(prim[0] > 0) || !(prim[4] > 0)) return fail(IGR_EINVAL, "jet needs rho > 0 and p > 0");
+    igr_patch& pa = ctx->patches[index];
+    pa.rho = prim[0];
+    pa.ux = prim[1];
+    pa.uy = prim[2];
+    pa.uz = prim[3];
+    pa.p = prim[4];
+    IGR_HIP(hipDeviceSynchronize());  // no queued kernel may still read the old table
+    return upload_jets(ctx, nullptr, true);
+}
+
+int igr_sigma_solve(igr_ctx* ctx, void* U, void* sigma, int32_t nsweeps, double* resid_l2, void* stream) {
+    if (!ctx || !U || !sigma) return fail(IGR_EINVAL, "null argument");
+    if (nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
+    return DISPATCH(ctx, sigma_t, ctx, U, sigma, nsweeps, resid_l2, as_stream(stream));
+}
+
+int igr_rhs(igr_ctx* ctx, void* U, void* sigma, void* rhs, void* stream) {
+    if (!ctx || !U || !sigma || !rhs) return fail(IGR_EINVAL, "null argument");
+    if (rhs == U || rhs == sigma) return fail(IGR_EINVAL, "rhs must not alias U or sigma");
+    return DISPATCH(ctx, rhs_t, ctx, U, sigma, rhs, as_stream(stream));
+}
+
+int igr_step(igr_ctx* ctx, void* U, void* sigma, double cfl, double dt_fixed, double* dt_used, void* stream) {
+    if (!ctx || !U || !sigma) return fail(IGR_EINVAL, "null argument");
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(IGR_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(DISPATCH(ctx, step_t, ctx, U, sigma, cfl, dt_fixed, s));
+    if (dt_used) {
+        if (dt_fixed > 0.0) {
+            *dt_used = dt_fixed;
+        } else {
+            IGR_HIP(hipMemcpyAsync(dt_used, ctx->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        return read_flag(ctx, s);
+    }
+    return IGR_OK;
+}
+
+int igr_compute_dt(igr_ctx* ctx, const void* U, double cfl, double* dt, void* stream) {
+    if (!ctx || !U || !dt) return fail(IGR_EINVAL, "null argument");
+    if (!(cfl > 0.0)) return fail(IGR_EINVAL, "cfl must be > 0");
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(DISPATCH(ctx, dt_t, ctx, U, cfl, s));
+    IGR_HIP(hipMemcpyAsync(dt, ctx->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+    return read_flag(ctx, s);
+}
+
+int igr_sums(igr_ctx* ctx, const void* U, double out[5], void* stream) {
+    if (!ctx || !U || !out) return fail(IGR_EINVAL, "null argument");
+    return DISPATCH(ctx, sums_t, ctx, U, out, as_stream(stream));
+}
+
+int igr_check(igr_ctx* ctx, void* stream) {
+    if (!ctx) return fail(IGR_EINVAL, "null context");
+    return read_flag(ctx, as_stream(stream));
+}
+
+int igr_timing(igr_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(IGR_EINVAL, "null context");
+    if (enable && !ctx->timing) {
+        IGR_TRY(collect_timing(ctx));
+        for (int k = 0; k < K_COUNT; ++k) {
+            ctx->kernel_ms[k] = 0.0;
+            ctx->kernel_count[k] = 0;
+        }
+    }
+    ctx->timing = enable != 0;
+    return IGR_OK;
+}
+
+int igr_kernel_time(igr_ctx* ctx, const char* name, double* ms, int64_t* count) {
+    if (!ctx || !name) return fail(IGR_EINVAL, "null argument");
+    IGR_TRY(collect_timing(ctx));
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (std::strcmp(name, kKernelNames[k]) == 0) {
+            if (ms) *ms = ctx->kernel_ms[k];
+            if (count) *count = ctx->kernel_count[k];
+            return IGR_OK;
+        }
+    }
+    return fail(IGR_EINVAL, std::string("unknown kernel name ") + name);
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Device-side types and helpers shared by the libigr kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace igr {
+
+constexpr int G = 3;  // ghost layers (five-point upwind reconstruction)
+
+// bfloat16 storage word.  Values are widened to float for arithmetic and
+// rounded back to nearest-even once per store.
+struct bf16 {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x0040u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+// Storage type T -> arithmetic type C with load/store conversions.
+template <class T>
+struct Storage;
+
+template <>
+struct Storage<double> {
+    using C = double;
+    __device__ __forceinline__ static double load(const double* p) { return *p; }
+    __device__ __forceinline__ static void store(double* p, double v) { *p = v; }
+};
+
+template <>
+struct Storage<float> {
+    using C = float;
+    __device__ __forceinline__ static float load(const float* p) { return *p; }
+    __device__ __forceinline__ static void store(float* p, float v) { *p = v; }
+};
+
+template <>
+struct Storage<bf16> {
+    using C = float;
+    __device__ __forceinline__ static float load(const bf16* p) {
+        return __uint_as_float(uint32_t(p->bits) << 16);
+    }
+    __device__ __forceinline__ static void store(bf16* p, float v) { p->bits = f32_to_bf16_rne(v); }
+};
+
+// Padded-grid geometry passed by value to every kernel.
+struct Geom {
+    int n[3];          // interior extents nx, ny, nz
+    int st[3];         // strides of x, y, z in a padded field (1, px, px*py)
+    long long fs;      // elements per padded field
+    double ih[3];      // 1/dx, 1/dy, 1/dz
+    double gamma;
+    double alpha;
+    int periodic[3];
+};
+
+__device__ __forceinline__ long long cell_offset(const Geom& g, int i, int j, int k) {
+    return (long long)(k + G) * g.st[2] + (long long)(j + G) * g.st[1] + (i + G);
+}
+
+// Offset (relative to the cell) of the axis-d neighbour on side s (+1/-1)
+// for a field whose ghosts are NOT filled: periodic wrap or the cell itself
+// (zero gradient).
+__device__ __forceinline__ int neighbour_no_ghost(const Geom& g, int d, int idx, int s) {
+    const int n = g.n[d];
+    const int t = idx + s;
+    if (t >= 0 && t < n) return s * g.st[d];
+    if (g.periodic[d]) return (t < 0 ? (n - 1) : -(n - 1)) * g.st[d];
+    return 0;
+}
+
+}  // namespace igr

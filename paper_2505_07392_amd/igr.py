@@ -1,0 +1,258 @@
+"""ctypes binding of libigr (C ABI in include/igr.h).
+
+Argument marshalling only: every step of the solver runs in the HIP
+library.  PyTorch provides device memory (padded tensors) and the stream
+(``torch.cuda.current_stream()``); the library is loaded from this package
+directory and a missing library raises immediately, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import torch
+
+G = 3
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigr.so")
+
+IGR_OK, IGR_EINVAL, IGR_ENOMEM, IGR_EHIP, IGR_ENONFINITE, IGR_EUNSUPPORTED = range(6)
+BC_KIND = {"periodic": 0, "extrap": 1}
+PRECISION = {"f64": (0, torch.float64), "f32": (1, torch.float32), "bf16": (2, torch.bfloat16)}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class Patch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("yc", "zc", "r", "width", "rho", "ux", "uy", "uz", "p")]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("face", ctypes.c_int32 * 6), ("npatch", ctypes.c_int32), ("patch", ctypes.POINTER(Patch))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("nsweeps", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class IGRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libigr error {code}: {msg}")
+        self.code = code
+
+
+class NonFiniteError(IGRError):
+    pass
+
+
+_lib = None
+
+_SIGNATURES = {
+    "igr_init": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.c_double, ctypes.c_double, ctypes.POINTER(BC),
+                                ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "igr_finalize": (ctypes.c_int, [ctypes.c_void_p]),
+    "igr_last_error": (ctypes.c_char_p, []),
+    "igr_field_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "igr_set_patch_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "igr_sigma_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_rhs": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "igr_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_compute_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "igr_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "igr_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "igr_kernel_name": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libigr.so from the package directory (raises if not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_07392_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != IGR_OK:
+        msg = lib().igr_last_error().decode()
+        raise (NonFiniteError if rc == IGR_ENONFINITE else IGRError)(rc, msg)
+
+
+def kernel_names() -> list:
+    out, i = [], 0
+    while True:
+        n = lib().igr_kernel_name(i)
+        if not n:
+            return out
+        out.append(n.decode())
+        i += 1
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One libigr context: grid, boundary description, precision, sweeps."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, *, gamma: float = 1.4,
+                 alpha: float = 0.0, faces: Sequence[str] = ("extrap",) * 6, jets: Iterable = (),
+                 nsweeps: int = 5, precision: str = "f64", device=None):
+        if precision not in PRECISION:
+            raise ValueError(f"precision must be one of {list(PRECISION)}")
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.dx, self.dy, self.dz = dx, dy, dz
+        self.gamma, self.alpha, self.nsweeps = gamma, alpha, nsweeps
+        self.precision = precision
+        self.dtype = PRECISION[precision][1]
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.shape = (nz + 2 * G, ny + 2 * G, nx + 2 * G)
+        jets = list(jets)
+        self._patches = (Patch * max(1, len(jets)))()
+        for i, j in enumerate(jets):
+            self._patches[i] = Patch(j.yc, j.zc, j.r, getattr(j, "width", 0.0), j.rho, j.ux, j.uy, j.uz, j.p)
+        bc = BC((ctypes.c_int32 * 6)(*[BC_KIND[f] for f in faces]), len(jets), self._patches)
+        opts = Opts(PRECISION[precision][0], 5, nsweeps, 0)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().igr_init(ctypes.byref(Grid(nx, ny, nz, dx, dy, dz)), gamma, alpha, ctypes.byref(bc),
+                                  ctypes.byref(opts), ctypes.byref(handle)))
+        self._ctx = handle
+
+    @classmethod
+    def from_workload(cls, w, precision: str = "f64", nsweeps: Optional[int] = None, device=None) -> "Solver":
+        return cls(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha, faces=tuple(w.faces),
+                   jets=w.jets, nsweeps=w.nsweeps if nsweeps is None else nsweeps, precision=precision,
+                   device=device)
+
+    # -- memory ------------------------------------------------------------
+    def new_state(self) -> torch.Tensor:
+        return torch.zeros((5,) + self.shape, dtype=self.dtype, device=self.device)
+
+    def new_field(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+
+    @staticmethod
+    def interior(a: torch.Tensor) -> torch.Tensor:
+        return a[..., G:-G, G:-G, G:-G]
+
+    def state_from(self, U) -> torch.Tensor:
+        """Padded device state from an interior array [5, nz, ny, nx]."""
+        out = self.new_state()
+        self.interior(out).copy_(torch.as_tensor(U).to(dtype=torch.float64).to(self.dtype))
+        return out
+
+    def field_from(self, S) -> torch.Tensor:
+        out = self.new_field()
+        self.interior(out).copy_(torch.as_tensor(S).to(dtype=torch.float64).to(self.dtype))
+        return out
+
+    def _validate(self, t: torch.Tensor, nfields: int, name: str):
+        shape = ((nfields,) if nfields > 1 else ()) + self.shape
+        if tuple(t.shape) != shape or t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of shape {shape} on {self.device}, "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- solver calls --------------------------------------------------------
+    def sigma_solve(self, U: torch.Tensor, sigma: torch.Tensor, nsweeps: Optional[int] = None,
+                    residual: bool = False) -> Optional[float]:
+        self._validate(U, 5, "U")
+        self._validate(sigma, 1, "sigma")
+        r = ctypes.c_double(0.0)
+        _check(lib().igr_sigma_solve(self._ctx, _ptr(U), _ptr(sigma),
+                                     self.nsweeps if nsweeps is None else nsweeps,
+                                     ctypes.byref(r) if residual else None, self._stream()))
+        return r.value if residual else None
+
+    def rhs(self, U: torch.Tensor, sigma: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._validate(U, 5, "U")
+        self._validate(sigma, 1, "sigma")
+        out = self.new_state() if out is None else out
+        self._validate(out, 5, "rhs")
+        _check(lib().igr_rhs(self._ctx, _ptr(U), _ptr(sigma), _ptr(out), self._stream()))
+        return out
+
+    def step(self, U: torch.Tensor, sigma: torch.Tensor, cfl: float = 0.5, dt_fixed: float = 0.0,
+             sync: bool = True) -> Optional[float]:
+        """One SSP-RK3 step in place; returns dt (and checks the non-finite
+        flag) when sync is True."""
+        self._validate(U, 5, "U")
+        self._validate(sigma, 1, "sigma")
+        dt = ctypes.c_double(0.0)
+        _check(lib().igr_step(self._ctx, _ptr(U), _ptr(sigma), cfl, dt_fixed,
+                              ctypes.byref(dt) if sync else None, self._stream()))
+        return dt.value if sync else None
+
+    def compute_dt(self, U: torch.Tensor, cfl: float) -> float:
+        self._validate(U, 5, "U")
+        dt = ctypes.c_double(0.0)
+        _check(lib().igr_compute_dt(self._ctx, _ptr(U), cfl, ctypes.byref(dt), self._stream()))
+        return dt.value
+
+    def sums(self, U: torch.Tensor) -> list:
+        self._validate(U, 5, "U")
+        out = (ctypes.c_double * 5)()
+        _check(lib().igr_sums(self._ctx, _ptr(U), out, self._stream()))
+        return list(out)
+
+    def check(self):
+        _check(lib().igr_check(self._ctx, self._stream()))
+
+    def set_jet_state(self, index: int, rho: float, ux: float, uy: float, uz: float, p: float):
+        prim = (ctypes.c_double * 5)(rho, ux, uy, uz, p)
+        _check(lib().igr_set_patch_state(self._ctx, index, prim))
+
+    def timing(self, enable: bool):
+        _check(lib().igr_timing(self._ctx, 1 if enable else 0))
+
+    def kernel_time(self, name: str):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().igr_kernel_time(self._ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def run(self, U, sigma, cfl: float, t_end: float, max_steps: int = 10 ** 7):
+        """Advance to t_end with the CFL rule, clipping the last step.
+        Returns (t, steps)."""
+        t, n = 0.0, 0
+        while t < t_end and n < max_steps:
+            dt = self.compute_dt(U, cfl)
+            if t + dt > t_end:
+                dt = t_end - t
+            self.step(U, sigma, dt_fixed=dt, sync=True)
+            t += dt
+            n += 1
+        return t, n
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().igr_finalize(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

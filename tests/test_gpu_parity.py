@@ -1,0 +1,269 @@
+"""GPU parity of the HIP path (called through the C ABI) against the FP64
+oracle: rel L-inf <= 1e-12 per field.
+
+Small cases span several 64 x 4 thread tiles with ragged tails, mixed
+boundaries, jet discs, zero sweeps and one-cell axes; full-size cases
+(256^3 periodic box) are checked on sampled cells with the oracle run on a
+periodic window around each sample, plus properties that hold at any size
+(conservation, determinism, transverse exactness).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import igr_ref as ref
+from paper_2505_07392_amd import igr, inputs
+from helpers import problem_from
+from gpu_common import TOL, banner, rel_linf, to_host, window
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def _mixed_workload(nx, ny, nz, seed, amp=0.3, jets=True, faces=None):
+    U = inputs.random_state(nx, ny, nz, seed, amp=amp, umax=0.4)
+    dx = 1.0 / max(nx, ny, nz)
+    js = []
+    if jets:
+        js = [inputs.Jet(yc=0.3 * ny * dx, zc=0.4 * nz * dx, r=3.0 * dx, rho=0.6, ux=2.0, uy=0.1, uz=-0.1, p=2.0,
+                         width=1.5 * dx),
+              inputs.Jet(yc=0.75 * ny * dx, zc=0.7 * nz * dx, r=2.0 * dx, rho=0.8, ux=1.5, uy=0.0, uz=0.0, p=1.5,
+                         width=0.0)]
+    faces = faces or ("extrap", "extrap", "periodic", "periodic", "extrap", "extrap")
+    return inputs.Workload("mixed", nx, ny, nz, dx, 1.1 * dx, 0.9 * dx, U, alpha=0.7 * dx * dx, faces=faces,
+                           jets=js, nsweeps=5)
+
+
+CASES = {
+    "mixed_70x9x7": lambda: _mixed_workload(70, 9, 7, 0),
+    "periodic_8cube": lambda: _mixed_workload(8, 8, 8, 1, jets=False, faces=("periodic",) * 6),
+    "extrap_33x5x3": lambda: _mixed_workload(33, 5, 3, 2, jets=False, faces=("extrap",) * 6),
+    "thin_axis_65x1x6": lambda: _mixed_workload(65, 1, 6, 3, jets=False,
+                                                faces=("extrap", "extrap", "periodic", "periodic", "periodic", "periodic")),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    w = CASES[request.param]()
+    return request.param, w
+
+
+def _sigma0(w, seed=7):
+    return np.random.default_rng(seed).random((w.nz, w.ny, w.nx)) * 0.1
+
+
+@pytest.mark.parametrize("nsweeps", [0, 1, 5])
+def test_sigma_solve(case, nsweeps):
+    name, w = case
+    banner(f"sigma_solve {name} nsweeps={nsweeps}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    res = s.sigma_solve(U, sig, nsweeps=nsweeps, residual=True)
+    prob = problem_from(w)
+    want, _ = ref.sigma_solve(prob, torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)), nsweeps=nsweeps)
+    assert rel_linf(to_host(s, sig), want.numpy()).max() <= TOL
+    want_res = ref.sigma_residual_l2(prob, torch.from_numpy(w.U), want)
+    assert abs(res - want_res) <= 1e-10 * max(want_res, 1e-300)
+
+
+def test_rhs(case):
+    name, w = case
+    banner(f"rhs {name}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    L = s.rhs(U, sig)
+    prob = problem_from(w)
+    Lw, sw = ref.rhs(prob, torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)))
+    err = rel_linf(to_host(s, L), Lw.numpy())
+    assert err.max() <= TOL, err
+    assert rel_linf(to_host(s, sig), sw.numpy()).max() <= TOL
+    # interior of U untouched
+    assert np.array_equal(to_host(s, U), w.U)
+
+
+def test_step_cfl(case):
+    name, w = case
+    w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 11, amp=0.1, umax=0.3))
+    banner(f"step x3 {name}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    prob = problem_from(w)
+    Uo, so = torch.from_numpy(w.U.copy()), torch.from_numpy(_sigma0(w))
+    for n in range(3):
+        dt_o = ref.compute_dt(prob, Uo, 0.5)
+        dt_g = s.step(U, sig, cfl=0.5)
+        assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+        Uo, so = ref.rk3_step(prob, Uo, so, dt_o)
+    err = rel_linf(to_host(s, U), Uo.numpy())
+    assert err.max() <= TOL, err
+    assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
+
+
+def test_dt_and_sums(case):
+    name, w = case
+    banner(f"dt/sums {name}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    prob = problem_from(w)
+    dt = s.compute_dt(U, 0.37)
+    want = ref.compute_dt(prob, torch.from_numpy(w.U), 0.37)
+    assert abs(dt - want) <= 1e-15 * want
+    sums = np.array(s.sums(U))
+    want_s = ref.conserved_sums(prob, torch.from_numpy(w.U)).numpy()
+    scale = np.abs(w.U).sum(axis=(1, 2, 3)) * w.dx * w.dy * w.dz
+    assert (np.abs(sums - want_s) <= 1e-14 * scale).all()
+
+
+def test_sod_full_run_and_transverse_exactness():
+    w = inputs.sod()                                # 128 x 16 x 16, t = 0.2
+    banner("sod 128x16x16 to t=0.2")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    t, n = s.run(U, sig, w.cfl, w.t_end)
+    Ug = to_host(s, U)
+    # exact uniformity across y and z, zero transverse momentum
+    assert np.array_equal(Ug, np.broadcast_to(Ug[:, :1, :1, :], Ug.shape))
+    assert np.count_nonzero(Ug[2]) == 0 and np.count_nonzero(Ug[3]) == 0
+    # oracle on 128 x 2 x 2 computes the identical column (y/z faces cancel exactly)
+    wo = inputs.sod(nx=128, ny=2, nz=2)
+    prob = problem_from(wo)
+    Uo, so, to, no = ref.run(prob, torch.from_numpy(wo.U), torch.zeros(prob.shape, dtype=torch.float64),
+                             wo.cfl, wo.t_end)
+    assert n == no and abs(t - to) <= 1e-15
+    err = rel_linf(Ug[:, :2, :2, :], Uo.numpy())
+    assert err[[0, 1, 4]].max() <= TOL, err
+
+
+def test_periodic_box_steps():
+    w = inputs.periodic_box(n=32, seed=1)
+    banner("periodic box 32^3, 5 steps")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    prob = problem_from(w)
+    Uo, so = torch.from_numpy(w.U.copy()), torch.zeros(prob.shape, dtype=torch.float64)
+    for _ in range(5):
+        dt = s.step(U, sig, cfl=0.5)
+        Uo, so = ref.rk3_step(prob, Uo, so, ref.compute_dt(prob, Uo, 0.5))
+    assert rel_linf(to_host(s, U), Uo.numpy()).max() <= TOL
+    assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
+
+
+def test_jets_steps_and_patch_update():
+    w = inputs.multi_jet(n=32, jets_per_side=2, radius_cells=4.0, mach=3.0, nsweeps=10, nx=40)
+    banner("jets 40x32x32, 6 steps, then a new jet pressure")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    prob = problem_from(w)
+    Uo, so = torch.from_numpy(w.U.copy()), torch.zeros(prob.shape, dtype=torch.float64)
+    for _ in range(6):
+        s.step(U, sig, cfl=0.5)
+        Uo, so = ref.rk3_step(prob, Uo, so, ref.compute_dt(prob, Uo, 0.5))
+    assert rel_linf(to_host(s, U), Uo.numpy()).max() <= TOL
+    j = w.jets[1]
+    s.set_jet_state(1, j.rho, j.ux, j.uy, j.uz, 6.5)
+    prob.patches[1].p = 6.5
+    L = s.rhs(U, sig)
+    Lw, sw = ref.rhs(prob, Uo, so)
+    assert rel_linf(to_host(s, L), Lw.numpy()).max() <= TOL
+
+
+def test_determinism_bitwise():
+    w = _mixed_workload(70, 9, 7, 5)
+    banner("determinism")
+    s = igr.Solver.from_workload(w)
+    outs = []
+    for _ in range(2):
+        U = s.state_from(w.U)
+        sig = s.field_from(_sigma0(w))
+        s.step(U, sig, cfl=0.4)
+        outs.append((to_host(s, U), to_host(s, sig)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("bad", ["negative_rho", "nan_energy"])
+def test_nonfinite_state_is_reported(bad):
+    w = _mixed_workload(16, 8, 8, 6, jets=False)
+    banner(f"non-finite {bad}")
+    U0 = w.U.copy()
+    if bad == "negative_rho":
+        U0[0, 3, 4, 5] = -1.0
+    else:
+        U0[4, 2, 2, 2] = float("nan")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(U0)
+    sig = s.new_field()
+    with pytest.raises(igr.NonFiniteError):
+        s.step(U, sig, dt_fixed=1e-4)
+    s.check()   # the flag was cleared by the report
+
+
+# ---------------------------------------------------------------------------
+# Full size: 256^3 periodic box (the measured workload)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def box256():
+    return inputs.periodic_box(n=256, seed=0)
+
+
+def test_full_size_rhs_sampled(box256):
+    w = box256
+    banner("rhs 256^3 sampled")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    L = to_host(s, s.rhs(U, sig))
+    Sg = to_host(s, sig)
+    rng = np.random.default_rng(42)
+    R = 11                       # flux 3 + sweeps 5 + source 1, plus margin
+    Lmax = np.abs(L).reshape(5, -1).max(axis=1)
+    pts = [tuple(rng.integers(0, 256, 3)) for _ in range(6)] + [(0, 0, 0), (255, 255, 255)]
+    for p in pts:
+        win = window(w.U, p, R)
+        n = 2 * R + 1
+        prob = ref.Problem(n, n, n, w.dx, w.dy, w.dz, alpha=w.alpha, faces=("periodic",) * 6, nsweeps=w.nsweeps)
+        Lw, sw = ref.rhs(prob, torch.from_numpy(win), torch.zeros((n, n, n), dtype=torch.float64))
+        k, j, i = p
+        assert (np.abs(L[:, k, j, i] - Lw[:, R, R, R].numpy()) <= TOL * Lmax).all(), p
+        assert abs(Sg[k, j, i] - float(sw[R, R, R])) <= TOL * np.abs(Sg).max()
+
+
+def test_full_size_step_sampled_and_conservation(box256):
+    w = box256
+    banner("step 256^3 sampled + 100-step conservation")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    prob_full = problem_from(w)
+    dt = ref.compute_dt(prob_full, torch.from_numpy(w.U), 0.5)
+    assert abs(s.compute_dt(U, 0.5) - dt) <= 1e-14 * dt
+    s0 = np.array(s.sums(U))
+    s.step(U, sig, dt_fixed=dt)
+    Ug = to_host(s, U)
+    R = 29                      # three stages of the rhs dependency radius
+    n = 2 * R + 1
+    prob = ref.Problem(n, n, n, w.dx, w.dy, w.dz, alpha=w.alpha, faces=("periodic",) * 6, nsweeps=w.nsweeps)
+    rng = np.random.default_rng(3)
+    scale = np.abs(Ug).reshape(5, -1).max(axis=1)
+    for p in [tuple(rng.integers(0, 256, 3)) for _ in range(2)]:
+        Uw, _ = ref.rk3_step(prob, torch.from_numpy(window(w.U, p, R)), torch.zeros((n, n, n), dtype=torch.float64), dt)
+        k, j, i = p
+        assert (np.abs(Ug[:, k, j, i] - Uw[:, R, R, R].numpy()) <= TOL * scale).all(), p
+    for _ in range(99):
+        s.step(U, sig, cfl=0.5, sync=False)
+    s.check()
+    drift = np.abs(np.array(s.sums(U)) - s0)
+    mag = np.abs(Ug).reshape(5, -1).sum(axis=1) * w.dx ** 3
+    assert (drift <= 1e-12 * mag).all(), drift / mag
