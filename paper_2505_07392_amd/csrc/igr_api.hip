@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "igr.h"
+#include "igr_flux.h"
 #include "igr_kernels.h"
 
 using namespace igr;
@@ -176,11 +177,37 @@ int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
     return fill_sigma_ghosts(c, sig, s);
 }
 
+// Launch shape of the tiled flux kernel: 64 x TY column tiles, z chunks
+// sized for >= ~2048 blocks (256 CUs, several resident blocks each).
+constexpr int FLUX_TY = 4;
+
+struct FluxLaunch {
+    int tiles_x, tiles_y, zc, chunks;
+    long long blocks() const { return (long long)tiles_x * tiles_y * chunks; }
+};
+
+FluxLaunch flux_launch(const Geom& g) {
+    FluxLaunch L;
+    L.tiles_x = (g.n[0] + FLUX_TX - 1) / FLUX_TX;
+    L.tiles_y = (g.n[1] + FLUX_TY - 1) / FLUX_TY;
+    const long long tiles = (long long)L.tiles_x * L.tiles_y;
+    long long zc = (tiles * g.n[2] + 2047) / 2048;
+    if (zc < 4) zc = 4;
+    if (zc > 64) zc = 64;
+    if (zc > g.n[2]) zc = g.n[2];
+    L.zc = int(zc);
+    L.chunks = (g.n[2] + L.zc - 1) / L.zc;
+    return L;
+}
+
 template <class T, int MODE>
 int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
               hipStream_t s) {
+    const FluxLaunch L = flux_launch(c->g);
+    if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
-        k_flux<T, MODE><<<cell_grid(c->g), cell_block(), 0, s>>>(U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag);
+        k_flux_tiled<T, MODE, FLUX_TY><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, FLUX_TY + 1), 0, s>>>(
+            U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
     });
 }
 

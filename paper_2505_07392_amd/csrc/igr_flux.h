@@ -1,0 +1,252 @@
+// Tiled, z-marching fused flux kernel.
+//
+// One block owns a 64 x TY column tile of the x-y plane and marches through
+// a chunk of z planes.  For each plane k:
+//   A  the plane (six fields rho, m, E, Sigma, with a three-cell x/y halo)
+//      is staged in LDS: interior cells from the register queue of each
+//      thread's column, halo cells from global memory (L2);
+//   B  every face is computed once: x faces (i+1/2) and y faces (j-1/2)
+//      from the LDS plane, the z face (k+1/2) from the column's register
+//      queue of planes k-2..k+3; x/y face fluxes go to LDS;
+//   C  each cell takes the flux differences, forms L(U) and the SSP-RK3
+//      stage combination, and stores the result.
+// The block has TY+1 waves: wave w < TY owns row w of the tile; wave TY
+// computes the extra row of y faces and the x faces at the tile's left
+// edge.  All faces of one direction run through one instruction sequence,
+// so equal inputs give bitwise equal fluxes (a uniform state stays exactly
+// uniform, transverse momentum of a planar problem stays exactly zero).
+#pragma once
+
+#include "igr_kernels.h"
+
+namespace igr {
+
+constexpr int FLUX_TX = 64;
+
+// Block index -> logical tile index such that consecutive logical tiles run
+// on the same XCD (blocks are dealt round-robin to the 8 XCDs), so a tile's
+// y-halo rows are usually still in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int NX = 8;
+    const int full = nb - nb % NX;
+    if (b >= full) return b;
+    const int per = full / NX;
+    return (b % NX) * per + b / NX;
+}
+
+template <class C>
+__device__ __forceinline__ void face_flux6(const C (&v)[6][6], int d, C gamma, C F[5], bool& bad) {
+    C UL[5], UR[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        UL[f] = recon_left(v[f][0], v[f][1], v[f][2], v[f][3], v[f][4]);
+        UR[f] = recon_right(v[f][1], v[f][2], v[f][3], v[f][4], v[f][5]);
+    }
+    const C SL = recon_left(v[5][0], v[5][1], v[5][2], v[5][3], v[5][4]);
+    const C SR = recon_right(v[5][1], v[5][2], v[5][3], v[5][4], v[5][5]);
+    llf_flux<C>(UL, UR, SL, SR, d, gamma, F, bad);
+}
+
+template <class T, int MODE, int TY>
+__global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
+    const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out, const double* __restrict__ dtp,
+    double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc) {
+    using S = Storage<T>;
+    using C = typename S::C;
+    constexpr int TX = FLUX_TX;
+    constexpr int W = TX + 2 * G;
+    constexpr int H = TY + 2 * G;
+    __shared__ C pl[6][H][W];
+    __shared__ C fx[5][TY][TX + 1];
+    __shared__ C fy[5][TY + 1][TX];
+
+    const int lane = threadIdx.x;
+    const int wv = threadIdx.y;
+    const int nthreads = TX * (TY + 1);
+    const int tid = wv * TX + lane;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int cz = b / tiles_y;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = cz * zc;
+    const int z1 = min(z0 + zc, nz);
+    const long long fs = g.fs;
+    const int sy = g.st[1], sz = g.st[2];
+    const C gamma = C(g.gamma);
+    const C ihx = C(g.ih[0]), ihy = C(g.ih[1]), ihz = C(g.ih[2]);
+    const C dt = C(dtp ? *dtp : dt_fixed);
+
+    // this thread's column (waves < TY): loads padded cells that exist
+    const int i = x0 + lane;
+    const int j = y0 + wv;
+    const bool own = wv < TY;
+    const bool col_load = own && i < nx + G && j < ny + G;
+    const bool col_out = own && i < nx && j < ny;
+    const long long col = (long long)(j + G) * sy + (i + G);
+
+    // register queue: planes k-2 .. k+3 of the six fields (index 0..5)
+    C q[6][6];
+    C Fz_prev[5];
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int p = 0; p < 6; ++p) q[f][p] = C(0);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) Fz_prev[f] = C(0);
+
+    auto load_col = [&](int plane, C (&v)[6]) {
+        const long long o = col + (long long)(plane + G) * sz;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[f] = S::load(U + f * fs + o);
+        v[5] = S::load(Sg + o);
+    };
+    // prime with planes z0-3 .. z0+2 (slot p holds plane z0-3+p; the loop
+    // below starts with one shift, at k = z0 - 1 computing face z0 - 1/2)
+    if (col_load) {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            C v[6];
+            load_col(z0 - 3 + p, v);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) q[f][p + 1] = v[f];
+        }
+    }
+
+    for (int k = z0 - 1; k < z1; ++k) {
+        // shift the queue and load plane k+3 (slot 5) so slots hold k-2..k+3
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int p = 0; p < 5; ++p) q[f][p] = q[f][p + 1];
+        if (col_load) {
+            C v[6];
+            load_col(k + 3, v);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) q[f][5] = v[f];
+        }
+        const bool body = k >= z0;
+        if (body) {
+            // A: stage plane k in LDS (interior from the queue, halo from memory)
+            if (own) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pl[f][wv + G][lane + G] = q[f][2];
+            }
+            {
+                constexpr int NXH = 2 * G * TY;          // x-halo cells per field
+                constexpr int NYH = 2 * G * TX;          // y-halo cells per field
+                constexpr int NH = NXH + NYH;
+                const long long zo = (long long)(k + G) * sz;
+                for (int h = tid; h < 6 * NH; h += nthreads) {
+                    const int f = h / NH;
+                    const int r = h - f * NH;
+                    int cx, cy;  // tile-relative (0 = tile origin)
+                    if (r < NXH) {
+                        cy = r / (2 * G);
+                        const int c = r - cy * 2 * G;
+                        cx = c < G ? c - G : TX + (c - G);
+                    } else {
+                        const int r2 = r - NXH;
+                        const int rr = r2 / TX;
+                        cx = r2 - rr * TX;
+                        cy = rr < G ? rr - G : TY + (rr - G);
+                    }
+                    const int gx = x0 + cx, gy = y0 + cy;
+                    if (gx >= -G && gx < nx + G && gy >= -G && gy < ny + G) {
+                        const long long o = zo + (long long)(gy + G) * sy + (gx + G);
+                        pl[f][cy + G][cx + G] = f < 5 ? S::load(U + f * fs + o) : S::load(Sg + o);
+                    }
+                }
+            }
+            __syncthreads();
+            // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv; wave TY,
+            // lanes < TY: face x0-1/2 of row `lane`.  One code path.
+            {
+                const int r = own ? wv : lane;
+                const int fi = own ? lane + 1 : 0;       // face index: face (x0 + fi - 1/2)
+                const int gxf = x0 + fi - 1;             // cell left of the face
+                const bool act = (own || lane < TY) && (y0 + r) < ny && gxf >= -1 && gxf < nx;
+                if (act) {
+                    C v[6][6];
+#pragma unroll
+                    for (int f = 0; f < 6; ++f)
+#pragma unroll
+                        for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi - 1 + p + 1];
+                    C F[5];
+                    face_flux6<C>(v, 0, gamma, F, bad);
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) fx[f][r][fi] = F[f];
+                }
+            }
+            // B2: y faces (y0+wv)-1/2 for wv = 0..TY, column lane
+            {
+                const int gyf = y0 + wv;                 // cell above the face
+                const bool act = (x0 + lane) < nx && gyf >= 0 && gyf <= ny;
+                if (act) {
+                    C v[6][6];
+#pragma unroll
+                    for (int f = 0; f < 6; ++f)
+#pragma unroll
+                        for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
+                    C F[5];
+                    face_flux6<C>(v, 1, gamma, F, bad);
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) fy[f][wv][lane] = F[f];
+                }
+            }
+        }
+        // B3: z face k+1/2 from the queue (also at k = z0-1 to prime Fz_prev)
+        C Fz[5];
+        if (col_out) {
+            C v[6][6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+#pragma unroll
+                for (int p = 0; p < 6; ++p) v[f][p] = q[f][p];
+            face_flux6<C>(v, 2, gamma, Fz, bad);
+        }
+        if (body) {
+            __syncthreads();
+            // C: divergence and stage update
+            if (col_out) {
+                const long long o = col + (long long)(k + G) * sz;
+                C L[5];
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    C l = C(0);
+                    l -= (fx[f][wv][lane + 1] - fx[f][wv][lane]) * ihx;
+                    l -= (fy[f][wv + 1][lane] - fy[f][wv][lane]) * ihy;
+                    l -= (Fz[f] - Fz_prev[f]) * ihz;
+                    L[f] = l;
+                }
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    const long long of = f * fs + o;
+                    C v;
+                    if (MODE == MODE_RHS) {
+                        v = L[f];
+                    } else if (MODE == MODE_STAGE1) {
+                        v = q[f][2] + dt * L[f];
+                    } else if (MODE == MODE_STAGE2) {
+                        v = C(0.75) * S::load(Un + of) + C(0.25) * (q[f][2] + dt * L[f]);
+                    } else {
+                        v = S::load(Un + of) / C(3) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
+                    }
+                    S::store(out + of, v);
+                }
+            }
+        }
+        if (col_out) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) Fz_prev[f] = Fz[f];
+        }
+        // the next iteration overwrites pl only after every wave passed the
+        // second barrier above, and fx/fy only after its first barrier
+    }
+    if (bad) flag[0] = 1;
+}
+
+}  // namespace igr

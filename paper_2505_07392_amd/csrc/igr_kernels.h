@@ -5,8 +5,8 @@
 //   k_bc_sigma   ghost layers of Sigma (periodic or zero gradient)
 //   k_source     b = alpha [tr((grad u)^2) + tr^2(grad u)], eq. (9) left side
 //   k_jacobi     one Jacobi sweep of eq. (9)'s 7-point discretisation
-//   k_flux       fifth-order reconstruction + LLF flux with p + Sigma +
-//                divergence, fused with the SSP-RK3 stage combination
+//   (the fused reconstruction + LLF flux + divergence + SSP-RK3 stage kernel
+//    is k_flux_tiled in igr_flux.h)
 //   k_*_partial  deterministic FP64 block reductions (dt, sums, residual)
 #pragma once
 
@@ -195,66 +195,6 @@ __device__ __forceinline__ void llf_flux(const C UL[5], const C UR[5], C SL, C S
         F[1 + c] = C(0.5) * (fl + fr) - C(0.5) * lam * (UR[1 + c] - UL[1 + c]);
     }
     F[4] = C(0.5) * ((UL[4] + ptl) * unl + (UR[4] + ptr) * unr) - C(0.5) * lam * (UR[4] - UL[4]);
-}
-
-// One thread per interior cell: the two faces of each direction (both
-// recomputed), L(U) = -sum_d (F+ - F-)/h_d, then the stage combination.
-// Reads U and Sigma with three filled ghost layers.  `Un` is read
-// pointwise for stages 2 and 3; `out` may alias `Un` (stage 3 in place).
-template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_flux(const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out,
-                       const double* __restrict__ dtp, double dt_fixed, Geom g, int* __restrict__ flag) {
-    using S = Storage<T>;
-    using C = typename S::C;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long long o = cell_offset(g, i, j, k);
-    const C gamma = C(g.gamma);
-    C L[5] = {C(0), C(0), C(0), C(0), C(0)};
-    bool bad = false;
-    for (int d = 0; d < 3; ++d) {
-        const int sd = g.st[d];
-        C q[6][7];
-        for (int p = 0; p < 7; ++p) {
-            const long long op = o + (long long)(p - 3) * sd;
-            for (int f = 0; f < 5; ++f) q[f][p] = S::load(U + f * g.fs + op);
-            q[5][p] = S::load(Sg + op);
-        }
-        C ULm[5], URm[5], ULp[5], URp[5];
-        for (int f = 0; f < 5; ++f) {
-            ULm[f] = recon_left(q[f][0], q[f][1], q[f][2], q[f][3], q[f][4]);
-            URm[f] = recon_right(q[f][1], q[f][2], q[f][3], q[f][4], q[f][5]);
-            ULp[f] = recon_left(q[f][1], q[f][2], q[f][3], q[f][4], q[f][5]);
-            URp[f] = recon_right(q[f][2], q[f][3], q[f][4], q[f][5], q[f][6]);
-        }
-        const C SLm = recon_left(q[5][0], q[5][1], q[5][2], q[5][3], q[5][4]);
-        const C SRm = recon_right(q[5][1], q[5][2], q[5][3], q[5][4], q[5][5]);
-        const C SLp = recon_left(q[5][1], q[5][2], q[5][3], q[5][4], q[5][5]);
-        const C SRp = recon_right(q[5][2], q[5][3], q[5][4], q[5][5], q[5][6]);
-        C Fm[5], Fp[5];
-        llf_flux<C>(ULm, URm, SLm, SRm, d, gamma, Fm, bad);
-        llf_flux<C>(ULp, URp, SLp, SRp, d, gamma, Fp, bad);
-        const C ih = C(g.ih[d]);
-        for (int f = 0; f < 5; ++f) L[f] -= (Fp[f] - Fm[f]) * ih;
-    }
-    if (bad) flag[0] = 1;
-    const C dt = C(dtp ? *dtp : dt_fixed);
-    for (int f = 0; f < 5; ++f) {
-        const long long of = f * g.fs + o;
-        C v;
-        if (MODE == MODE_RHS) {
-            v = L[f];
-        } else if (MODE == MODE_STAGE1) {
-            v = S::load(U + of) + dt * L[f];
-        } else if (MODE == MODE_STAGE2) {
-            v = C(0.75) * S::load(Un + of) + C(0.25) * (S::load(U + of) + dt * L[f]);
-        } else {
-            v = S::load(Un + of) / C(3) + (C(2) / C(3)) * (S::load(U + of) + dt * L[f]);
-        }
-        S::store(out + of, v);
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -43,6 +43,7 @@ CASES = {
     "mixed_70x9x7": lambda: _mixed_workload(70, 9, 7, 0),
     "periodic_8cube": lambda: _mixed_workload(8, 8, 8, 1, jets=False, faces=("periodic",) * 6),
     "extrap_33x5x3": lambda: _mixed_workload(33, 5, 3, 2, jets=False, faces=("extrap",) * 6),
+    "chunks_130x10x40": lambda: _mixed_workload(130, 10, 40, 4, amp=0.2),
     "thin_axis_65x1x6": lambda: _mixed_workload(65, 1, 6, 3, jets=False,
                                                 faces=("extrap", "extrap", "periodic", "periodic", "periodic", "periodic")),
 }
@@ -190,6 +191,23 @@ def test_determinism_bitwise():
         s.step(U, sig, cfl=0.4)
         outs.append((to_host(s, U), to_host(s, sig)))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("faces", [("periodic",) * 6, ("extrap",) * 6])
+def test_uniform_state_is_stationary_bitwise(faces):
+    """Every face of a direction computes the same flux from the same
+    inputs, so a uniform state has L(U) = 0 exactly."""
+    nx, ny, nz = 70, 9, 11
+    U0 = np.empty((5, nz, ny, nx))
+    for f, v in enumerate((0.9, 0.3, -0.4, 0.2, 3.1)):
+        U0[f] = v
+    w = inputs.Workload("uniform", nx, ny, nz, 0.1, 0.2, 0.3, U0, alpha=0.01, faces=faces, nsweeps=3)
+    banner(f"uniform state {faces[0]}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(U0)
+    sig = s.field_from(np.full((nz, ny, nx), 0.37))
+    L = to_host(s, s.rhs(U, sig))
+    assert np.count_nonzero(L) == 0
 
 
 @pytest.mark.parametrize("bad", ["negative_rho", "nan_energy"])
