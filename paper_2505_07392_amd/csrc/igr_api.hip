@@ -11,6 +11,7 @@
 
 #include "igr.h"
 #include "igr_flux.h"
+#include "igr_sigma.h"
 #include "igr_kernels.h"
 
 using namespace igr;
@@ -155,26 +156,89 @@ int fill_sigma_ghosts(igr_ctx* c, T* Sg, hipStream_t s) {
     return IGR_OK;
 }
 
-// Source + nsweeps Jacobi sweeps from `sig` (warm start).  U ghosts must be
-// filled.  The last iterate ends in `sig` (a device copy follows an odd
-// number of sweeps); its ghosts are then filled.
+// Sigma passes: `nsweeps` Jacobi sweeps split into passes of at most
+// SigShape<T>::KMAX levels of the temporally blocked kernel (each pass
+// reads rho, m and Sigma once and forms the source itself).  FP64 uses a
+// shorter tile (fewer threads per block, more registers per thread).
+#ifndef IGR_SIG_KMAX_F64
+#define IGR_SIG_KMAX_F64 3
+#endif
+#ifndef IGR_SIG_NR_F64
+#define IGR_SIG_NR_F64 12
+#endif
+#ifndef IGR_SIG_KMAX_F32
+#define IGR_SIG_KMAX_F32 5
+#endif
+#ifndef IGR_SIG_NR_F32
+#define IGR_SIG_NR_F32 16
+#endif
+template <class T>
+struct SigShape {
+    static constexpr int KMAX = IGR_SIG_KMAX_F32;
+    static constexpr int NR = IGR_SIG_NR_F32;
+};
+template <>
+struct SigShape<double> {
+    static constexpr int KMAX = IGR_SIG_KMAX_F64;
+    static constexpr int NR = IGR_SIG_NR_F64;
+};
+
+template <class T, int K>
+int sigma_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
+    constexpr int NR = SigShape<T>::NR;
+    constexpr int TXo = SIG_TX - 2 * K, TYo = NR - 2 * K;
+    const int tiles_x = (c->g.n[0] + TXo - 1) / TXo;
+    const int tiles_y = (c->g.n[1] + TYo - 1) / TYo;
+    const long long tiles = (long long)tiles_x * tiles_y;
+    long long zc = (tiles * c->g.n[2] + 1023) / 1024;   // aim at >= ~1024 blocks
+    if (zc < 16) zc = 16;
+    if (zc > 128) zc = 128;
+    if (zc > c->g.n[2]) zc = c->g.n[2];
+    const long long chunks = (c->g.n[2] + zc - 1) / zc;
+    const long long blocks = tiles * chunks;
+    if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the Sigma launch");
+    return launch(c, K_JACOBI, s, [&] {
+        k_sigma_march<T, K, NR><<<dim3(unsigned(blocks)), dim3(SIG_TX, NR), 0, s>>>(U, Sin, Sout, c->g, tiles_x,
+                                                                                  tiles_y, int(zc));
+    });
+}
+
+template <class T>
+int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream_t s) {
+    constexpr int KM = SigShape<T>::KMAX;
+    if (k >= 5 && KM >= 5) return sigma_pass<T, (KM >= 5 ? 5 : 1)>(c, U, Sin, Sout, s);
+    if (k >= 4 && KM >= 4) return sigma_pass<T, (KM >= 4 ? 4 : 1)>(c, U, Sin, Sout, s);
+    if (k >= 3 && KM >= 3) return sigma_pass<T, (KM >= 3 ? 3 : 1)>(c, U, Sin, Sout, s);
+    if (k >= 2 && KM >= 2) return sigma_pass<T, (KM >= 2 ? 2 : 1)>(c, U, Sin, Sout, s);
+    return sigma_pass<T, 1>(c, U, Sin, Sout, s);
+}
+
+// nsweeps Jacobi sweeps from `sig` (warm start); U ghosts must be filled.
+// The last iterate ends in `sig` (device copy after an odd number of
+// passes) and its ghosts are filled.
 template <class T>
 int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
-    using C = typename Storage<T>::C;
-    C* b = static_cast<C*>(c->d_b);
-    IGR_TRY(launch(c, K_SOURCE, s, [&] { k_source<T, C><<<cell_grid(c->g), cell_block(), 0, s>>>(U, b, c->g); }));
     T* src = sig;
     T* dst = static_cast<T*>(c->d_sig2);
-    for (int it = 0; it < nsweeps; ++it) {
-        IGR_TRY(launch(c, K_JACOBI, s, [&] {
-            k_jacobi<T, C><<<cell_grid(c->g), cell_block(), 0, s>>>(src, dst, b, U, c->g);
-        }));
+    int left = nsweeps;
+    while (left > 0) {
+        const int k = left < SigShape<T>::KMAX ? left : SigShape<T>::KMAX;
+        IGR_TRY(sigma_pass_k<T>(c, k, U, src, dst, s));
+        left -= k;
         T* tmp = src;
         src = dst;
         dst = tmp;
     }
     if (src != sig) IGR_HIP(hipMemcpyAsync(sig, src, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
     return fill_sigma_ghosts(c, sig, s);
+}
+
+// Source b into the scratch array (for the residual diagnostic).
+template <class T>
+int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
+    using C = typename Storage<T>::C;
+    C* b = static_cast<C*>(c->d_b);
+    return launch(c, K_SOURCE, s, [&] { k_source<T, C><<<cell_grid(c->g), cell_block(), 0, s>>>(U, b, c->g); });
 }
 
 // Launch shape of the tiled flux kernel: 64 x TY column tiles, z chunks
@@ -371,7 +435,7 @@ int sigma_t(igr_ctx* c, void* U, void* sig, int nsweeps, double* resid, hipStrea
     IGR_TRY(fill_state_ghosts(c, static_cast<T*>(U), s));
     IGR_TRY(sigma_solve_impl(c, static_cast<T*>(U), static_cast<T*>(sig), nsweeps, s));
     if (resid) {
-        // the source of the final U is still in d_b
+        IGR_TRY(source_impl(c, static_cast<const T*>(U), s));
         IGR_TRY(resid_impl(c, static_cast<const T*>(U), static_cast<const T*>(sig), resid, s));
     }
     return IGR_OK;
