@@ -112,6 +112,85 @@ def run_form(w, precision, steps, warmup):
     return el, kt
 
 
+def jet_workload(n: int, nsteps: int):
+    from paper_2505_07392_amd import inputs
+
+    w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10, nsteps=nsteps)
+    w.alpha = 4.0 * w.dx * w.dx     # Mach-3 jets need alpha = 4 dx^2 (alpha = dx^2 loses positivity)
+    return w
+
+
+def rel_l1(a, b):
+    import torch
+
+    return [float((a[f] - b[f]).abs().sum() / b[f].abs().sum()) if float(b[f].abs().sum()) > 0 else 0.0
+            for f in range(a.shape[0])]
+
+
+def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
+    """Multi-jet box: rate of each precision form, footprint, and per-field
+    rel L1 error of FP32 / BF16 against the FP64 run after `nsteps` steps
+    with the same fixed dt."""
+    import torch
+
+    from paper_2505_07392_amd import igr
+
+    w = jet_workload(n, nsteps)
+    out = {"workload": f"multi_jet_{n}", "cells": w.cells, "steps": nsteps, "alpha_dx2": 4.0, "sweeps": w.nsweeps,
+           "forms": {}}
+    finals = {}
+    for prec in forms:
+        print(f"[bench] multi-jet {n}^3 {prec}", file=sys.stderr, flush=True)
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        s = igr.Solver.from_workload(w, precision=prec)
+        U = s.state_from(w.U)
+        S = s.new_field()
+        dt = 0.8 * s.compute_dt(U, w.cfl) if "dt" not in out else out["dt"]
+        out.setdefault("dt", dt)
+        free, total = torch.cuda.mem_get_info()
+        for _ in range(warmup):
+            s.step(U, S, dt_fixed=dt, sync=False)
+        torch.cuda.synchronize()
+        s.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(timed_steps):
+            s.step(U, S, dt_fixed=dt, sync=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.timing(False)
+        s.check()
+        kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
+        form = {"value": w.cells * timed_steps / el, "ms_per_step": 1e3 * el / timed_steps,
+                "device_bytes_in_use": total - free, "frac_of_288GB": (total - free) / 288e9}
+        esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+        csz = 8 if prec == "f64" else 4
+        for k in ("flux_rk", "jacobi"):
+            ms, cnt = kt[k]
+            if cnt:
+                ab = algorithmic_bytes_per_cell(k, esz, csz, w.nsweeps) * w.cells
+                form[k] = {"avg_ms": ms / cnt, "achieved_GBs": ab / (ms / cnt / 1e3) / 1e9,
+                           "frac": ab / (ms / cnt / 1e3) / 1e9 / HBM_PEAK_GBS}
+        # full-length run from the initial state for the error table
+        if nsteps > 0:
+            U = s.state_from(w.U)
+            S = s.new_field()
+            for _ in range(nsteps):
+                s.step(U, S, dt_fixed=dt, sync=False)
+            s.check()
+            finals[prec] = torch.cat([s.interior(U).double(), s.interior(S).double()[None]]).cpu()
+        out["forms"][prec] = form
+        del U, S
+        s.close()
+        torch.cuda.empty_cache()
+    if "f64" in finals:
+        for prec in finals:
+            if prec != "f64":
+                out["forms"][prec]["rel_l1_vs_f64"] = dict(zip(["rho", "mx", "my", "mz", "E", "Sigma"],
+                                                               rel_l1(finals[prec], finals["f64"])))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +200,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--forms", default="f32,bf16", help="extra precision forms timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
@@ -132,6 +212,10 @@ def main():
     from paper_2505_07392_amd import igr, inputs
 
     torch.cuda.set_device(0)
+    if args.study:
+        _, n, nst, forms = args.study.split(":")
+        study_jets(int(n), int(nst), forms.split(","), args.steps, args.warmup)
+        return
     print(f"[bench] generating the {args.n}^3 periodic box", file=sys.stderr, flush=True)
     w = inputs.periodic_box(n=args.n, seed=0)
     print(f"[bench] timing {args.precision}: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)

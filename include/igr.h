@@ -166,6 +166,31 @@ int igr_rhs(igr_ctx *ctx, void *U, void *sigma, void *rhs, void *stream);
 int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, double *dt_used,
              void *stream);
 
+/* Discrete adjoint of igr_rhs (FP64 contexts; vector-Jacobian product of
+ * the map (U, sigma_prev) -> (L(U), sigma_new) and of the jet-disc
+ * states).  Given rhs_bar (5 fields) and sigma_bar (cotangent of the new
+ * Sigma), writes U_bar (5 fields) and sigma_prev_bar; only interiors are
+ * read, outputs have zero ghosts.  patch_bar (nullable, host, npatch*5)
+ * receives the cotangents of the primitive jet states (rho, ux, uy, uz, p).
+ * The LLF maximum passes its cotangent to the larger wave speed (half to
+ * each on a tie) and |u_n| uses sign(u_n).  U's ghosts are rewritten.
+ * Inputs may alias outputs.  Scratch (about 70 + nsweeps FP64 fields) is
+ * allocated on the first call and kept by the context.  Synchronises. */
+int igr_rhs_adjoint(igr_ctx *ctx, void *U, const void *sigma_prev, const void *rhs_bar, const void *sigma_bar,
+                    void *U_bar, void *sigma_prev_bar, double *patch_bar, void *stream);
+
+/* Discrete adjoint of one igr_step with a fixed time step dt > 0 (FP64):
+ * given the step's input (U_n, sigma_n) and the cotangents of its output
+ * (U_bar_np1, sigma_bar_np1), writes the cotangents of its input (U_bar_n,
+ * sigma_bar_n) and, if patch_bar is not NULL, of the primitive jet states
+ * (npatch*5, host).  The three stage states and Sigma iterates are
+ * recomputed from U_n inside the call (no storage between calls), so a
+ * multi-step gradient needs only the per-step inputs (checkpointing).
+ * Conventions, aliasing and scratch as igr_rhs_adjoint.  Synchronises. */
+int igr_step_adjoint(igr_ctx *ctx, void *U_n, const void *sigma_n, double dt, const void *U_bar_np1,
+                     const void *sigma_bar_np1, void *U_bar_n, void *sigma_bar_n, double *patch_bar,
+                     void *stream);
+
 /* FP64 CFL time step of state U (rule as in igr_step; synchronises). */
 int igr_compute_dt(igr_ctx *ctx, const void *U, double cfl, double *dt, void *stream);
 

@@ -12,6 +12,7 @@
 #include "igr.h"
 #include "igr_flux.h"
 #include "igr_sigma.h"
+#include "igr_adjoint.h"
 #include "igr_kernels.h"
 
 using namespace igr;
@@ -39,9 +40,9 @@ int fail(int code, const std::string& msg) {
         if (rc_ != IGR_OK) return rc_; \
     } while (0)
 
-enum KernelId { K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_COUNT };
-const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source", "jacobi",
-                                           "flux_rk",  "dt",       "sums",   "resid"};
+enum KernelId { K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_SWEEP, K_ADJOINT, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source", "jacobi", "flux_rk",
+                                           "dt",       "sums",     "resid",  "sweep",  "adjoint"};
 
 struct TimingRecord {
     int kernel;
@@ -61,6 +62,7 @@ struct igr_ctx {
     size_t esize = 8;     // storage bytes per element
     size_t csize = 8;     // arithmetic bytes per element (source array)
     std::vector<igr_patch> patches;
+    std::vector<int> h_owner;     // per x-min column (k*ny + j): nearest disc or -1
     int* d_owner = nullptr;
     double* d_chi = nullptr;
     double* d_jet = nullptr;
@@ -76,6 +78,9 @@ struct igr_ctx {
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[K_COUNT] = {};
     long long kernel_count[K_COUNT] = {};
+    // adjoint scratch (FP64, allocated on first adjoint call)
+    int adj_sweeps = -1;
+    std::vector<double*> adj;     // see adjoint_buffers()
 };
 
 namespace {
@@ -379,6 +384,7 @@ int upload_patches(igr_ctx* c) {
             }
         }
     }
+    c->h_owner = owner;
     IGR_HIP(hipMemcpy(c->d_owner, owner.data(), owner.size() * sizeof(int), hipMemcpyHostToDevice));
     IGR_HIP(hipMemcpy(c->d_chi, chi.data(), chi.size() * sizeof(double), hipMemcpyHostToDevice));
     return IGR_OK;
@@ -405,6 +411,8 @@ void release(igr_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->d_owner, c->d_chi, c->d_jet, c->d_Ua, c->d_Ub, c->d_sig2, c->d_b, c->d_partial, c->d_scalars, c->d_flag};
     for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (double* p : c->adj)
         if (p) (void)hipFree(p);
     for (auto& r : c->records) {
         c->event_pool.push_back(r.start);
@@ -447,6 +455,161 @@ int dt_t(igr_ctx* c, const void* U, double cfl, hipStream_t s) {
 template <class T>
 int sums_t(igr_ctx* c, const void* U, double* out, hipStream_t s) {
     return sums_impl(c, static_cast<const T*>(U), out, s);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (FP64)
+// ---------------------------------------------------------------------------
+
+// Adjoint scratch: fields of the padded size (index -> role)
+enum AdjBuf {
+    A_U1, A_U2 = A_U1 + 5, A_SIG1 = A_U2 + 5, A_SIG2, A_SPAD, A_UBPAD, A_SBPAD = A_UBPAD + 5, A_FA,
+    A_NB = A_FA + 12, A_DB, A_BB, A_IR, A_IRB, A_LB, A_UST = A_LB + 5, A_SBA = A_UST + 5, A_SBB, A_UBN,
+    A_UB1 = A_UBN + 5, A_UB2 = A_UB1 + 5, A_UBIN = A_UB2 + 5, A_SBIN = A_UBIN + 5, A_ITER
+};
+
+int adjoint_buffers(igr_ctx* c) {
+    const int S = c->nsweeps;
+    if (c->adj_sweeps == S) return IGR_OK;
+    for (double* p : c->adj)
+        if (p) (void)hipFree(p);
+    c->adj.clear();
+    const int nfield = A_ITER + S + 1;
+    double* base = nullptr;
+    hipError_t e = hipMalloc((void**)&base, (size_t)nfield * field_bytes(c, sizeof(double)) +
+                                               (size_t)c->ny * c->nz * 5 * sizeof(double));
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? IGR_ENOMEM : IGR_EHIP,
+                                     std::string("adjoint scratch: ") + hipGetErrorString(e));
+    c->adj.push_back(base);
+    IGR_HIP(hipMemset(base, 0, (size_t)nfield * field_bytes(c, sizeof(double))));
+    c->adj_sweeps = S;
+    return IGR_OK;
+}
+
+double* abuf(igr_ctx* c, int idx) { return c->adj[0] + (size_t)idx * c->g.fs; }
+double* ajetcol(igr_ctx* c) { return c->adj[0] + (size_t)(A_ITER + c->nsweeps + 1) * c->g.fs; }
+
+dim3 padded_grid(const Geom& g) { return dim3((g.n[0] + 2 * G + 63) / 64, (g.n[1] + 2 * G + 3) / 4, g.n[2] + 2 * G); }
+
+int axpby(igr_ctx* c, double a, const double* x, double b, double* y, int nf, hipStream_t s) {
+    return launch(c, K_ADJOINT, s, [&] { k_axpby<<<cell_grid(c->g), cell_block(), 0, s>>>(a, x, b, y, nf, c->g); });
+}
+
+int dcopy(igr_ctx* c, double* dst, const double* src, int nf, hipStream_t s) {
+    IGR_HIP(hipMemcpyAsync(dst, src, (size_t)nf * field_bytes(c, sizeof(double)), hipMemcpyDeviceToDevice, s));
+    return IGR_OK;
+}
+
+int dzero(igr_ctx* c, double* p, int nf, hipStream_t s) {
+    IGR_HIP(hipMemsetAsync(p, 0, (size_t)nf * field_bytes(c, sizeof(double)), s));
+    return IGR_OK;
+}
+
+// Adjoint of one right-hand side (L, Sigma_new) = RHS(U, Sigma_p):
+// given L-bar (Lb, 5 fields) and Sigma_new-bar (Sbn), write U-bar (Ub_out,
+// interior, 5 fields) and Sigma_p-bar (Sbp_out, interior); add the x-min
+// jet cotangents (conserved, per patch) to jbar.
+int stage_adjoint(igr_ctx* c, double* U, const double* Sp, const double* Lb, const double* Sbn, double* Ub_out,
+                  double* Sbp_out, std::vector<double>& jbar, hipStream_t s) {
+    const Geom& g = c->g;
+    const int S = c->nsweeps;
+    double* ir = abuf(c, A_IR);
+    double* Spad = abuf(c, A_SPAD);
+    double* Ubpad = abuf(c, A_UBPAD);
+    double* Sbpad = abuf(c, A_SBPAD);
+    double* FA = abuf(c, A_FA);
+    double* Nb = abuf(c, A_NB);
+    double* Db = abuf(c, A_DB);
+    double* bb = abuf(c, A_BB);
+    double* irb = abuf(c, A_IRB);
+    double* sbA = abuf(c, A_SBA);
+    double* sbB = abuf(c, A_SBB);
+    auto iter = [&](int k) { return abuf(c, A_ITER + k); };
+    // forward recompute: ghosts, 1/rho, the S sweep iterates
+    IGR_TRY(fill_state_ghosts(c, U, s));
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] { k_inv_rho<<<padded_grid(g), cell_block(), 0, s>>>(U, ir, g); }));
+    IGR_TRY(dcopy(c, iter(0), Sp, 1, s));
+    IGR_TRY(source_impl(c, (const double*)U, s));
+    for (int k = 1; k <= S; ++k)
+        IGR_TRY(launch(c, K_SWEEP, s, [&] {
+            k_jacobi<double, double><<<cell_grid(g), cell_block(), 0, s>>>(iter(k - 1), iter(k),
+                                                                           (const double*)c->d_b, U, g);
+        }));
+    IGR_TRY(dcopy(c, Spad, iter(S), 1, s));
+    IGR_TRY(fill_sigma_ghosts(c, Spad, s));
+    // flux: per direction, face cotangents then the transposed stencil
+    IGR_TRY(dzero(c, Ubpad, 5, s));
+    IGR_TRY(dzero(c, Sbpad, 1, s));
+    for (int d = 0; d < 3; ++d) {
+        const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        const long long lines = (long long)g.n[a] * g.n[b];
+        const int bf = int((lines * (g.n[d] + 1) + 255) / 256);
+        const int bg = int((lines * (g.n[d] + 2 * G) + 255) / 256);
+        IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+            if (d == 0) {
+                k_adj_face<0><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
+                k_adj_recon_gather<0><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+            } else if (d == 1) {
+                k_adj_face<1><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
+                k_adj_recon_gather<1><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+            } else {
+                k_adj_face<2><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
+                k_adj_recon_gather<2><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+            }
+        }));
+    }
+    // Sigma ghosts transposed: sbA = Sigma^S-bar
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] { k_adj_sigma_bc<<<cell_grid(g), cell_block(), 0, s>>>(Sbpad, Sbn, sbA, g); }));
+    // Jacobi levels in reverse
+    IGR_TRY(dzero(c, bb, 1, s));
+    IGR_TRY(dzero(c, irb, 1, s));
+    for (int k = S; k >= 1; --k) {
+        IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+            k_adj_jac1<<<cell_grid(g), cell_block(), 0, s>>>(sbA, iter(k), ir, Nb, Db, bb, g);
+            k_adj_jac2<<<padded_grid(g), cell_block(), 0, s>>>(Nb, Db, iter(k - 1), ir, sbB, irb, g);
+        }));
+        double* t = sbA;
+        sbA = sbB;
+        sbB = t;
+    }
+    IGR_TRY(dcopy(c, Sbp_out, sbA, 1, s));
+    // source, 1/rho, ghosts of U
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+        k_adj_source<<<padded_grid(g), cell_block(), 0, s>>>(U, ir, bb, Ubpad, irb, g);
+        k_adj_irho<<<padded_grid(g), cell_block(), 0, s>>>(ir, irb, Ubpad, g);
+    }));
+    const bool inflow = !c->patches.empty();
+    double* jc = ajetcol(c);
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+        k_adj_bc_state<<<cell_grid(g), cell_block(), 0, s>>>(Ubpad, Ub_out, inflow ? c->d_owner : nullptr, c->d_chi,
+                                                             inflow ? jc : nullptr, g);
+    }));
+    if (inflow) {
+        const size_t cols = (size_t)c->ny * c->nz;
+        std::vector<double> h(cols * 5);
+        IGR_HIP(hipMemcpyAsync(h.data(), jc, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        IGR_HIP(hipStreamSynchronize(s));
+        for (size_t col = 0; col < cols; ++col) {
+            const int q = c->h_owner[col];
+            if (q < 0) continue;
+            for (int f = 0; f < 5; ++f) jbar[(size_t)q * 5 + f] += h[col * 5 + f];
+        }
+    }
+    return IGR_OK;
+}
+
+// conserved jet cotangents -> primitive (rho, ux, uy, uz, p) cotangents
+void jet_primitive_bar(const igr_ctx* c, const std::vector<double>& jbar, double* out) {
+    const double g1 = c->g.gamma - 1.0;
+    for (size_t q = 0; q < c->patches.size(); ++q) {
+        const igr_patch& pa = c->patches[q];
+        const double* J = &jbar[q * 5];
+        const double u[3] = {pa.ux, pa.uy, pa.uz};
+        const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        out[q * 5 + 0] = J[0] + J[1] * u[0] + J[2] * u[1] + J[3] * u[2] + J[4] * ke;
+        for (int k = 0; k < 3; ++k) out[q * 5 + 1 + k] = J[1 + k] * pa.rho + J[4] * pa.rho * u[k];
+        out[q * 5 + 4] = J[4] / g1;
+    }
 }
 
 }  // namespace
@@ -659,6 +822,91 @@ int igr_kernel_time(igr_ctx* ctx, const char* name, double* ms, int64_t* count) 
         }
     }
     return fail(IGR_EINVAL, std::string("unknown kernel name ") + name);
+}
+
+int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* rhs_bar, const void* sigma_bar,
+                    void* U_bar, void* sigma_prev_bar, double* patch_bar, void* stream) {
+    if (!ctx || !U || !sigma_prev || !rhs_bar || !sigma_bar || !U_bar || !sigma_prev_bar)
+        return fail(IGR_EINVAL, "null argument");
+    if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(adjoint_buffers(ctx));
+    // inputs may alias outputs: stage them
+    double* Lb = abuf(ctx, A_LB);
+    double* Sbn = abuf(ctx, A_SBIN);
+    IGR_TRY(dcopy(ctx, Lb, (const double*)rhs_bar, 5, s));
+    IGR_TRY(dcopy(ctx, Sbn, (const double*)sigma_bar, 1, s));
+    std::vector<double> jbar(ctx->patches.size() * 5, 0.0);
+    double* Ust = abuf(ctx, A_UST);
+    IGR_TRY(dzero(ctx, (double*)U_bar, 5, s));
+    IGR_TRY(dzero(ctx, (double*)sigma_prev_bar, 1, s));
+    IGR_TRY(stage_adjoint(ctx, (double*)U, (const double*)sigma_prev, Lb, Sbn, Ust, abuf(ctx, A_SBIN), jbar, s));
+    IGR_TRY(axpby(ctx, 1.0, Ust, 0.0, (double*)U_bar, 5, s));
+    IGR_TRY(axpby(ctx, 1.0, abuf(ctx, A_SBIN), 0.0, (double*)sigma_prev_bar, 1, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    if (patch_bar) jet_primitive_bar(ctx, jbar, patch_bar);
+    return IGR_OK;
+}
+
+int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, const void* U_bar_np1,
+                     const void* sigma_bar_np1, void* U_bar_n, void* sigma_bar_n, double* patch_bar, void* stream) {
+    if (!ctx || !U_n || !sigma_n || !U_bar_np1 || !sigma_bar_np1 || !U_bar_n || !sigma_bar_n)
+        return fail(IGR_EINVAL, "null argument");
+    if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
+    if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(adjoint_buffers(ctx));
+    const int S = ctx->nsweeps;
+    double* Un = (double*)U_n;
+    double* U1 = abuf(ctx, A_U1);
+    double* U2 = abuf(ctx, A_U2);
+    double* sig1 = abuf(ctx, A_SIG1);
+    double* sig2 = abuf(ctx, A_SIG2);
+    double* Ub3 = abuf(ctx, A_UBIN);
+    double* Sb3 = abuf(ctx, A_SBIN);
+    IGR_TRY(dcopy(ctx, Ub3, (const double*)U_bar_np1, 5, s));
+    IGR_TRY(dcopy(ctx, Sb3, (const double*)sigma_bar_np1, 1, s));
+    // forward recompute of the stage states and stage warm starts
+    IGR_TRY(fill_state_ghosts(ctx, Un, s));
+    IGR_TRY(dcopy(ctx, sig1, (const double*)sigma_n, 1, s));
+    IGR_TRY(sigma_solve_impl(ctx, Un, sig1, S, s));
+    IGR_TRY((flux_impl<double, MODE_STAGE1>(ctx, Un, sig1, nullptr, U1, nullptr, dt, s)));
+    IGR_TRY(fill_state_ghosts(ctx, U1, s));
+    IGR_TRY(dcopy(ctx, sig2, sig1, 1, s));
+    IGR_TRY(sigma_solve_impl(ctx, U1, sig2, S, s));
+    IGR_TRY((flux_impl<double, MODE_STAGE2>(ctx, U1, sig2, Un, U2, nullptr, dt, s)));
+    // reverse sweep over the stages
+    double* Ubn = abuf(ctx, A_UBN);
+    double* Ub1 = abuf(ctx, A_UB1);
+    double* Ub2 = abuf(ctx, A_UB2);
+    double* Lb = abuf(ctx, A_LB);
+    double* Ust = abuf(ctx, A_UST);
+    double* sbs = abuf(ctx, A_SBIN);   // running Sigma-bar (stage outputs -> inputs)
+    std::vector<double> jbar(ctx->patches.size() * 5, 0.0);
+    // stage 3: U3 = Un/3 + 2/3 (U2 + dt L(U2, Sigma2))
+    IGR_TRY(axpby(ctx, 1.0 / 3.0, Ub3, 0.0, Ubn, 5, s));
+    IGR_TRY(axpby(ctx, 2.0 / 3.0, Ub3, 0.0, Ub2, 5, s));
+    IGR_TRY(axpby(ctx, 2.0 / 3.0 * dt, Ub3, 0.0, Lb, 5, s));
+    IGR_TRY(stage_adjoint(ctx, U2, sig2, Lb, sbs, Ust, sbs, jbar, s));
+    IGR_TRY(axpby(ctx, 1.0, Ust, 1.0, Ub2, 5, s));
+    // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1, Sigma1))
+    IGR_TRY(axpby(ctx, 0.75, Ub2, 1.0, Ubn, 5, s));
+    IGR_TRY(axpby(ctx, 0.25, Ub2, 0.0, Ub1, 5, s));
+    IGR_TRY(axpby(ctx, 0.25 * dt, Ub2, 0.0, Lb, 5, s));
+    IGR_TRY(stage_adjoint(ctx, U1, sig1, Lb, sbs, Ust, sbs, jbar, s));
+    IGR_TRY(axpby(ctx, 1.0, Ust, 1.0, Ub1, 5, s));
+    // stage 1: U1 = Un + dt L(Un, Sigma_n)
+    IGR_TRY(axpby(ctx, 1.0, Ub1, 1.0, Ubn, 5, s));
+    IGR_TRY(axpby(ctx, dt, Ub1, 0.0, Lb, 5, s));
+    IGR_TRY(stage_adjoint(ctx, Un, (const double*)sigma_n, Lb, sbs, Ust, sbs, jbar, s));
+    IGR_TRY(axpby(ctx, 1.0, Ust, 1.0, Ubn, 5, s));
+    IGR_TRY(dzero(ctx, (double*)U_bar_n, 5, s));
+    IGR_TRY(dzero(ctx, (double*)sigma_bar_n, 1, s));
+    IGR_TRY(axpby(ctx, 1.0, Ubn, 0.0, (double*)U_bar_n, 5, s));
+    IGR_TRY(axpby(ctx, 1.0, sbs, 0.0, (double*)sigma_bar_n, 1, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    if (patch_bar) jet_primitive_bar(ctx, jbar, patch_bar);
+    return IGR_OK;
 }
 
 }  // extern "C"

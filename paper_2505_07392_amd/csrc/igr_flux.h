@@ -104,8 +104,14 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         for (int f = 0; f < 5; ++f) v[f] = S::load(U + f * fs + o);
         v[5] = S::load(Sg + o);
     };
-    // prime with planes z0-3 .. z0+2 (slot p holds plane z0-3+p; the loop
-    // below starts with one shift, at k = z0 - 1 computing face z0 - 1/2)
+    // prime with planes z0-3 .. z0+1 (slot p holds plane z0-3+p) and keep
+    // plane z0+2 in `nxt`; every iteration shifts, moves `nxt` into slot 5
+    // and issues the load of the plane after it, so each column load has a
+    // whole iteration to arrive.  The loop starts at k = z0 - 1 to compute
+    // face z0 - 1/2 with the same code as every other z face.
+    C nxt[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) nxt[f] = C(0);
     if (col_load) {
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
@@ -114,53 +120,71 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
             for (int f = 0; f < 6; ++f) q[f][p + 1] = v[f];
         }
+        load_col(z0 + 2, nxt);
     }
 
-    for (int k = z0 - 1; k < z1; ++k) {
-        // shift the queue and load plane k+3 (slot 5) so slots hold k-2..k+3
+    // halo of the next plane, prefetched into registers (HPT values per thread)
+    constexpr int NXH = 2 * G * TY;          // x-halo cells per field
+    constexpr int NYH = 2 * G * TX;          // y-halo cells per field
+    constexpr int NH = NXH + NYH;
+    constexpr int HPT = (6 * NH + TX * (TY + 1) - 1) / (TX * (TY + 1));
+    auto halo_slot = [&](int s, int& f, int& cx, int& cy) -> bool {
+        const int h = tid + s * nthreads;
+        if (h >= 6 * NH) return false;
+        f = h / NH;
+        const int r = h - f * NH;
+        if (r < NXH) {
+            cy = r / (2 * G);
+            const int c = r - cy * 2 * G;
+            cx = c < G ? c - G : TX + (c - G);
+        } else {
+            const int r2 = r - NXH;
+            const int rr = r2 / TX;
+            cx = r2 - rr * TX;
+            cy = rr < G ? rr - G : TY + (rr - G);
+        }
+        const int gx = x0 + cx, gy = y0 + cy;
+        return gx >= -G && gx < nx + G && gy >= -G && gy < ny + G;
+    };
+    C hv[HPT];
+    auto load_halo = [&](int plane) {
+        const long long zo = (long long)(plane + G) * sz;
 #pragma unroll
-        for (int f = 0; f < 6; ++f)
+        for (int s = 0; s < HPT; ++s) {
+            int f, cx, cy;
+            hv[s] = C(0);
+            if (halo_slot(s, f, cx, cy)) {
+                const long long o = zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G);
+                hv[s] = f < 5 ? S::load(U + f * fs + o) : S::load(Sg + o);
+            }
+        }
+    };
+    load_halo(z0);
+
+    for (int k = z0 - 1; k < z1; ++k) {
+        // shift the queue; slots hold k-2..k+3 afterwards
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
 #pragma unroll
             for (int p = 0; p < 5; ++p) q[f][p] = q[f][p + 1];
-        if (col_load) {
-            C v[6];
-            load_col(k + 3, v);
-#pragma unroll
-            for (int f = 0; f < 6; ++f) q[f][5] = v[f];
+            q[f][5] = nxt[f];
         }
+        if (col_load && k + 1 < z1) load_col(k + 4, nxt);
         const bool body = k >= z0;
+        C unv[5];
         if (body) {
-            // A: stage plane k in LDS (interior from the queue, halo from memory)
+            // A: stage plane k in LDS (interior from the queue, halo from the
+            // prefetched registers), then prefetch the halo of plane k+1
             if (own) {
 #pragma unroll
                 for (int f = 0; f < 6; ++f) pl[f][wv + G][lane + G] = q[f][2];
             }
-            {
-                constexpr int NXH = 2 * G * TY;          // x-halo cells per field
-                constexpr int NYH = 2 * G * TX;          // y-halo cells per field
-                constexpr int NH = NXH + NYH;
-                const long long zo = (long long)(k + G) * sz;
-                for (int h = tid; h < 6 * NH; h += nthreads) {
-                    const int f = h / NH;
-                    const int r = h - f * NH;
-                    int cx, cy;  // tile-relative (0 = tile origin)
-                    if (r < NXH) {
-                        cy = r / (2 * G);
-                        const int c = r - cy * 2 * G;
-                        cx = c < G ? c - G : TX + (c - G);
-                    } else {
-                        const int r2 = r - NXH;
-                        const int rr = r2 / TX;
-                        cx = r2 - rr * TX;
-                        cy = rr < G ? rr - G : TY + (rr - G);
-                    }
-                    const int gx = x0 + cx, gy = y0 + cy;
-                    if (gx >= -G && gx < nx + G && gy >= -G && gy < ny + G) {
-                        const long long o = zo + (long long)(gy + G) * sy + (gx + G);
-                        pl[f][cy + G][cx + G] = f < 5 ? S::load(U + f * fs + o) : S::load(Sg + o);
-                    }
-                }
+#pragma unroll
+            for (int s = 0; s < HPT; ++s) {
+                int f, cx, cy;
+                if (halo_slot(s, f, cx, cy)) pl[f][cy + G][cx + G] = hv[s];
             }
+            if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
             // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv; wave TY,
             // lanes < TY: face x0-1/2 of row `lane`.  One code path.
@@ -209,6 +233,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             face_flux6<C>(v, 2, gamma, Fz, bad);
         }
         if (body) {
+            // Un is read pointwise; issue its loads before the barrier
+            if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
+                const long long o = col + (long long)(k + G) * sz;
+#pragma unroll
+                for (int f = 0; f < 5; ++f) unv[f] = col_out ? S::load(Un + f * fs + o) : C(0);
+            }
             __syncthreads();
             // C: divergence and stage update
             if (col_out) {
@@ -231,9 +261,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     } else if (MODE == MODE_STAGE1) {
                         v = q[f][2] + dt * L[f];
                     } else if (MODE == MODE_STAGE2) {
-                        v = C(0.75) * S::load(Un + of) + C(0.25) * (q[f][2] + dt * L[f]);
+                        v = C(0.75) * unv[f] + C(0.25) * (q[f][2] + dt * L[f]);
                     } else {
-                        v = S::load(Un + of) / C(3) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
+                        v = unv[f] * (C(1) / C(3)) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
                     }
                     S::store(out + of, v);
                 }

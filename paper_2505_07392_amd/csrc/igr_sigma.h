@@ -107,17 +107,28 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
     __syncthreads();
     const int pbeg = z0 - K;
     const int pend = z1 + K + 1;   // input planes pbeg .. pend-1 emit outputs z0 .. z1-1
-    for (int P = pbeg; P < pend; ++P) {
-        // ---- loads: rho, m at plane P; Sigma_0 at plane P-1
+    // inputs of plane P are loaded one iteration ahead (registers nr, nm*, ns)
+    auto load_inputs = [&](int P, C& r, C& a, C& b, C& c, C& sg) {
         const int pz = src_index(P, nz, g.periodic[2]);
         const int pzs = src_index(P - 1, nz, g.periodic[2]);
         const long long o = col + (long long)(pz + G) * sz;
-        const C rho = S::load(U + o);
+        r = S::load(U + o);
+        a = S::load(U + fs + o);
+        b = S::load(U + 2 * fs + o);
+        c = S::load(U + 3 * fs + o);
+        sg = S::load(Sin + col + (long long)(pzs + G) * sz);
+    };
+    C nr, nm0, nm1, nm2, ns;
+    load_inputs(pbeg, nr, nm0, nm1, nm2, ns);
+    for (int P = pbeg; P < pend; ++P) {
+        // ---- inputs: rho, m at plane P; Sigma_0 at plane P-1 (prefetched)
+        const C rho = nr;
         const C ir = C(1) / rho;
-        const C u0 = S::load(U + fs + o) * ir;
-        const C u1 = S::load(U + 2 * fs + o) * ir;
-        const C u2 = S::load(U + 3 * fs + o) * ir;
-        const C s0new = S::load(Sin + col + (long long)(pzs + G) * sz);
+        const C u0 = nm0 * ir;
+        const C u1 = nm1 * ir;
+        const C u2 = nm2 * ir;
+        const C s0new = ns;
+        if (P + 1 < pend) load_inputs(P + 1, nr, nm0, nm1, nm2, ns);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             uR[c][0] = uR[c][1];

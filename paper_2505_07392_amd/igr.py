@@ -65,6 +65,10 @@ _SIGNATURES = {
     "igr_rhs": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "igr_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_rhs_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_step_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_compute_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
@@ -127,6 +131,8 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.shape = (nz + 2 * G, ny + 2 * G, nx + 2 * G)
         jets = list(jets)
+        self.npatch = len(jets)
+        self.jets = [[j.rho, j.ux, j.uy, j.uz, j.p] for j in jets]
         self._patches = (Patch * max(1, len(jets)))()
         for i, j in enumerate(jets):
             self._patches[i] = Patch(j.yc, j.zc, j.r, getattr(j, "width", 0.0), j.rho, j.ux, j.uy, j.uz, j.p)
@@ -205,6 +211,31 @@ class Solver:
                               ctypes.byref(dt) if sync else None, self._stream()))
         return dt.value if sync else None
 
+    def rhs_adjoint(self, U, sigma_prev, rhs_bar, sigma_bar):
+        """Cotangents (U_bar, sigma_prev_bar, patch_bar [npatch, 5]) of one
+        right-hand side given (rhs_bar, sigma_bar)."""
+        for t, n, name in ((U, 5, "U"), (sigma_prev, 1, "sigma_prev"), (rhs_bar, 5, "rhs_bar"),
+                           (sigma_bar, 1, "sigma_bar")):
+            self._validate(t, n, name)
+        Ub, Sb = self.new_state(), self.new_field()
+        npatch = max(1, self.npatch)
+        pb = (ctypes.c_double * (5 * npatch))()
+        _check(lib().igr_rhs_adjoint(self._ctx, _ptr(U), _ptr(sigma_prev), _ptr(rhs_bar), _ptr(sigma_bar),
+                                     _ptr(Ub), _ptr(Sb), pb, self._stream()))
+        return Ub, Sb, torch.tensor(list(pb), dtype=torch.float64).reshape(npatch, 5)[: self.npatch]
+
+    def step_adjoint(self, U_n, sigma_n, dt: float, U_bar, sigma_bar):
+        """Cotangents (U_bar_n, sigma_bar_n, patch_bar [npatch, 5]) of one
+        fixed-dt step given the cotangents of its output."""
+        for t, n, name in ((U_n, 5, "U_n"), (sigma_n, 1, "sigma_n"), (U_bar, 5, "U_bar"), (sigma_bar, 1, "sigma_bar")):
+            self._validate(t, n, name)
+        Ub, Sb = self.new_state(), self.new_field()
+        npatch = max(1, self.npatch)
+        pb = (ctypes.c_double * (5 * npatch))()
+        _check(lib().igr_step_adjoint(self._ctx, _ptr(U_n), _ptr(sigma_n), dt, _ptr(U_bar), _ptr(sigma_bar),
+                                      _ptr(Ub), _ptr(Sb), pb, self._stream()))
+        return Ub, Sb, torch.tensor(list(pb), dtype=torch.float64).reshape(npatch, 5)[: self.npatch]
+
     def compute_dt(self, U: torch.Tensor, cfl: float) -> float:
         self._validate(U, 5, "U")
         dt = ctypes.c_double(0.0)
@@ -223,6 +254,7 @@ class Solver:
     def set_jet_state(self, index: int, rho: float, ux: float, uy: float, uz: float, p: float):
         prim = (ctypes.c_double * 5)(rho, ux, uy, uz, p)
         _check(lib().igr_set_patch_state(self._ctx, index, prim))
+        self.jets[index] = [rho, ux, uy, uz, p]
 
     def timing(self, enable: bool):
         _check(lib().igr_timing(self._ctx, 1 if enable else 0))
