@@ -33,7 +33,11 @@ def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int
         # stage 1 reads U (5) + Sigma (1), writes 5; stages 2 and 3 also read Un (5)
         return esize * (11 + 16 + 16) / 3.0
     if kernel == "jacobi":
-        return 3 * esize + csize          # Sigma_in, rho, b read; Sigma_out written
+        # per sweep, averaged over the first (reads rho, m, Sigma; writes
+        # Sigma, b) and the later sweeps (read Sigma, rho, b; write Sigma)
+        first = 5 * esize + esize + csize
+        later = 3 * esize + csize
+        return (first + (nsweeps - 1) * later) / nsweeps
     if kernel == "source":
         return 4 * esize + csize          # rho, m read; b written
     if kernel == "dt":
@@ -87,12 +91,12 @@ def cpu_baseline(w, seconds_target: float = 15.0):
                       f"seed as the 256^3 workload), {el:.1f} s"}
 
 
-def run_form(w, precision, steps, warmup):
+def run_form(w, precision, steps, warmup, sigma_block=0):
     import torch
 
     from paper_2505_07392_amd import igr
 
-    s = igr.Solver.from_workload(w, precision=precision)
+    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block)
     U = s.state_from(w.U)
     sig = s.new_field()
     for _ in range(warmup):
@@ -163,7 +167,7 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
         kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
         form = {"value": w.cells * timed_steps / el, "ms_per_step": 1e3 * el / timed_steps,
                 "device_bytes_in_use": total - free, "frac_of_288GB": (total - free) / 288e9}
-        esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+        esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[prec]
         csz = 8 if prec == "f64" else 4
         for k in ("flux_rk", "jacobi"):
             ms, cnt = kt[k]
@@ -197,10 +201,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--forms", default="f32,bf16", help="extra precision forms timed on the same workload")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--forms", default="f32,f16,bf16", help="extra precision forms timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
+    ap.add_argument("--sigma-block", type=int, default=0, help="sweeps fused per Sigma pass (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
@@ -220,10 +225,10 @@ def main():
     w = inputs.periodic_box(n=args.n, seed=0)
     print(f"[bench] timing {args.precision}: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)
     cells = w.cells
-    esize = {"f64": 8, "f32": 4, "bf16": 2}
-    csize = {"f64": 8, "f32": 4, "bf16": 4}
+    esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+    csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 
-    el, kt = run_form(w, args.precision, args.steps, args.warmup)
+    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block)
     value = cells * args.steps / el
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -246,7 +251,7 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x and x != args.precision]:
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, _ = run_form(w, f, args.steps, args.warmup)
+        e2, _ = run_form(w, f, args.steps, args.warmup, args.sigma_block)
         forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps}
 
     line = {

@@ -26,8 +26,11 @@
  * ((k+3)*(ny+6) + (j+3))*(nx+6) + (i+3).  A state U is five consecutive
  * fields (rho, rho*u, rho*v, rho*w, E); Sigma and scalar outputs are one
  * field.  The element type follows the context precision: double
- * (IGR_F64), float (IGR_F32) or uint16_t holding bfloat16
- * (IGR_BF16_F32: bfloat16 storage, float arithmetic).
+ * (IGR_F64), float (IGR_F32), uint16_t holding bfloat16 (IGR_BF16_F32:
+ * bfloat16 storage, float arithmetic) or IEEE binary16 (IGR_F16_F32: half
+ * storage, float arithmetic -- the storage form of the paper's "Mixed
+ * Precision" section).  Every stored value is rounded to nearest even once;
+ * dt, the conservation sums and the Jacobi residual are FP64 in every form.
  *
  * Ownership and streams
  * ---------------------
@@ -72,7 +75,7 @@ enum {
 
 enum { IGR_BC_PERIODIC = 0, IGR_BC_EXTRAP = 1 };
 
-enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2 };
+enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2, IGR_F16_F32 = 3 };
 
 /* Uniform rectilinear grid of nx*ny*nz interior cells with spacings dx, dy,
  * dz (paper, "Example simulation result": rectilinear grid).  Each extent
@@ -110,12 +113,16 @@ typedef struct {
 
 /* Options: storage/arithmetic precision, reconstruction order (5), Jacobi
  * sweeps per right-hand side (the paper uses up to 5: "Shock treatment with
- * information geometric regularization"), flags (0). */
+ * information geometric regularization"), and sigma_block, the number of
+ * sweeps fused into one pass over memory: 1 (default, also selected by 0)
+ * runs one z-marching sweep per pass with the source formed in the first;
+ * 2..5 run temporally blocked passes of up to that many sweeps (fewer
+ * bytes, more arithmetic per cell).  Results agree to rounding. */
 typedef struct {
     int32_t precision;
     int32_t order;
     int32_t nsweeps;
-    int32_t flags;
+    int32_t sigma_block;
 } igr_opts;
 
 typedef struct igr_ctx igr_ctx;

@@ -57,6 +57,7 @@ struct igr_ctx {
     double dx = 0, dy = 0, dz = 0;
     int precision = IGR_F64;
     int nsweeps = 5;
+    int sigma_block = 1;   // sweeps fused per Sigma pass (1: z-marching single sweeps)
     int faces[6] = {0, 0, 0, 0, 0, 0};
     int device = 0;
     size_t esize = 8;     // storage bytes per element
@@ -219,20 +220,46 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 }
 
 // nsweeps Jacobi sweeps from `sig` (warm start); U ghosts must be filled.
-// The last iterate ends in `sig` (device copy after an odd number of
-// passes) and its ghosts are filled.
+// sigma_block == 1: one z-marching sweep per pass, the source formed in
+// the first pass and stored; otherwise passes of up to sigma_block levels
+// of the temporally blocked kernel.  The last iterate ends in `sig` (device
+// copy after an odd number of passes) and its ghosts are filled.
 template <class T>
 int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
+    using C = typename Storage<T>::C;
     T* src = sig;
     T* dst = static_cast<T*>(c->d_sig2);
-    int left = nsweeps;
-    while (left > 0) {
-        const int k = left < SigShape<T>::KMAX ? left : SigShape<T>::KMAX;
-        IGR_TRY(sigma_pass_k<T>(c, k, U, src, dst, s));
-        left -= k;
-        T* tmp = src;
-        src = dst;
-        dst = tmp;
+    if (c->sigma_block <= 1) {
+        const Geom& g = c->g;
+        const long long tiles = (long long)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4);
+        long long zc = (tiles * g.n[2] + 2047) / 2048;
+        if (zc < 4) zc = 4;
+        if (zc > 64) zc = 64;
+        if (zc > g.n[2]) zc = g.n[2];
+        const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, unsigned((g.n[2] + zc - 1) / zc));
+        C* b = static_cast<C*>(c->d_b);
+        for (int it = 0; it < nsweeps; ++it) {
+            IGR_TRY(launch(c, K_JACOBI, s, [&] {
+                if (it == 0)
+                    k_sweep_z<T, true><<<grid, dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc));
+                else
+                    k_sweep_z<T, false><<<grid, dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc));
+            }));
+            T* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+    } else {
+        const int kmax = c->sigma_block < SigShape<T>::KMAX ? c->sigma_block : SigShape<T>::KMAX;
+        int left = nsweeps;
+        while (left > 0) {
+            const int k = left < kmax ? left : kmax;
+            IGR_TRY(sigma_pass_k<T>(c, k, U, src, dst, s));
+            left -= k;
+            T* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
     }
     if (src != sig) IGR_HIP(hipMemcpyAsync(sig, src, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
     return fill_sigma_ghosts(c, sig, s);
@@ -248,17 +275,26 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 
 // Launch shape of the tiled flux kernel: 64 x TY column tiles, z chunks
 // sized for >= ~2048 blocks (256 CUs, several resident blocks each).
-constexpr int FLUX_TY = 4;
+// Rows per tile: the block (TY+1 waves) must fill the waves one CU can
+// hold at the kernel's register use (FP64: 8 per CU, FP32: 12).
+template <class T>
+struct FluxShape {
+    static constexpr int TY = 5;
+};
+template <>
+struct FluxShape<double> {
+    static constexpr int TY = 7;
+};
 
 struct FluxLaunch {
     int tiles_x, tiles_y, zc, chunks;
     long long blocks() const { return (long long)tiles_x * tiles_y * chunks; }
 };
 
-FluxLaunch flux_launch(const Geom& g) {
+FluxLaunch flux_launch(const Geom& g, int ty) {
     FluxLaunch L;
     L.tiles_x = (g.n[0] + FLUX_TX - 1) / FLUX_TX;
-    L.tiles_y = (g.n[1] + FLUX_TY - 1) / FLUX_TY;
+    L.tiles_y = (g.n[1] + ty - 1) / ty;
     const long long tiles = (long long)L.tiles_x * L.tiles_y;
     long long zc = (tiles * g.n[2] + 2047) / 2048;
     if (zc < 4) zc = 4;
@@ -272,10 +308,11 @@ FluxLaunch flux_launch(const Geom& g) {
 template <class T, int MODE>
 int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
               hipStream_t s) {
-    const FluxLaunch L = flux_launch(c->g);
+    constexpr int TY = FluxShape<T>::TY;
+    const FluxLaunch L = flux_launch(c->g, TY);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
-        k_flux_tiled<T, MODE, FLUX_TY><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, FLUX_TY + 1), 0, s>>>(
+        k_flux_tiled<T, MODE, TY><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
             U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
     });
 }
@@ -426,9 +463,10 @@ void release(igr_ctx* c) {
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 #define DISPATCH(ctx, FN, ...)                                                                        \
-    ((ctx)->precision == IGR_F64   ? FN<double>(__VA_ARGS__)                                          \
-     : (ctx)->precision == IGR_F32 ? FN<float>(__VA_ARGS__)                                           \
-                                   : FN<bf16>(__VA_ARGS__))
+    ((ctx)->precision == IGR_F64    ? FN<double>(__VA_ARGS__)                                         \
+     : (ctx)->precision == IGR_F32  ? FN<float>(__VA_ARGS__)                                          \
+     : (ctx)->precision == IGR_F16_F32 ? FN<f16>(__VA_ARGS__)                                         \
+                                    : FN<bf16>(__VA_ARGS__))
 
 template <class T>
 int rhs_t(igr_ctx* c, void* U, void* sig, void* rhs, hipStream_t s) {
@@ -643,11 +681,12 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
         if (!(pa.r >= 0) || !(pa.width >= 0) || !(pa.rho > 0) || !(pa.p > 0))
             return fail(IGR_EINVAL, "inflow disc needs r >= 0, width >= 0, rho > 0, p > 0");
     }
-    if (opts->precision != IGR_F64 && opts->precision != IGR_F32 && opts->precision != IGR_BF16_F32)
+    if (opts->precision != IGR_F64 && opts->precision != IGR_F32 && opts->precision != IGR_BF16_F32 &&
+        opts->precision != IGR_F16_F32)
         return fail(IGR_EINVAL, "unknown precision");
     if (opts->order != 5) return fail(IGR_EUNSUPPORTED, "only fifth-order reconstruction is implemented");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
-    if (opts->flags != 0) return fail(IGR_EUNSUPPORTED, "flags must be 0");
+    if (opts->sigma_block < 0 || opts->sigma_block > 5) return fail(IGR_EINVAL, "sigma_block must be in 0..5");
 
     igr_ctx* c = new (std::nothrow) igr_ctx();
     if (!c) return fail(IGR_ENOMEM, "host allocation failed");
@@ -659,6 +698,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->dz = grid->dz;
     c->precision = opts->precision;
     c->nsweeps = opts->nsweeps;
+    c->sigma_block = opts->sigma_block == 0 ? 1 : opts->sigma_block;
     for (int f = 0; f < 6; ++f) c->faces[f] = bc->face[f];
     c->patches.assign(bc->patch, bc->patch + bc->npatch);
     const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;
@@ -680,7 +720,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     g.gamma = gamma;
     g.alpha = alpha;
     for (int d = 0; d < 3; ++d) g.periodic[d] = bc->face[2 * d] == IGR_BC_PERIODIC;
-    c->esize = c->precision == IGR_F64 ? 8 : c->precision == IGR_F32 ? 4 : 2;
+    c->esize = c->precision == IGR_F64 ? 8 : c->precision == IGR_F32 ? 4 : 2;   // BF16 and F16: 2
     c->csize = c->precision == IGR_F64 ? 8 : 4;
 
     auto alloc = [&](void** p, size_t bytes) -> int {

@@ -48,6 +48,17 @@ struct Storage<bf16> {
     __device__ __forceinline__ static void store(bf16* p, float v) { p->bits = f32_to_bf16_rne(v); }
 };
 
+// IEEE binary16 storage (the paper's storage precision), float arithmetic;
+// conversions round to nearest even.
+using f16 = _Float16;
+
+template <>
+struct Storage<f16> {
+    using C = float;
+    __device__ __forceinline__ static float load(const f16* p) { return float(*p); }
+    __device__ __forceinline__ static void store(f16* p, float v) { *p = f16(v); }
+};
+
 // Padded-grid geometry passed by value to every kernel.
 struct Geom {
     int n[3];          // interior extents nx, ny, nz

@@ -223,3 +223,110 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
 }
 
 }  // namespace igr
+
+namespace igr {
+
+// One Jacobi sweep per pass, z-marching: a 64 x 4 block of columns walks a
+// chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
+// registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
+// lanes and rows).  With FIRST the source b is formed in the same pass
+// (from rho and m, also z-marched) and written for the later sweeps.
+// Per cell: FIRST reads rho, m, Sigma and writes Sigma, b; later sweeps
+// read Sigma, rho, b and write Sigma.
+template <class T, bool FIRST>
+__global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
+                                                 T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
+                                                 Geom g, int zc) {
+    using S = Storage<T>;
+    using C = typename S::C;
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int z0 = blockIdx.z * zc;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    if (i >= nx || j >= ny) return;
+    const int z1 = min(z0 + zc, nz);
+    const long long fs = g.fs;
+    const int sy = g.st[1], sz = g.st[2];
+    const long long col = (long long)(j + G) * sy + (i + G);
+    const C alpha = C(g.alpha);
+    const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
+    const C half = C(0.5);
+    // x/y Sigma neighbours (no ghosts): offsets with wrap or self
+    const int oxm = neighbour_no_ghost(g, 0, i, -1), oxp = neighbour_no_ghost(g, 0, i, +1);
+    const int oym = neighbour_no_ghost(g, 1, j, -1), oyp = neighbour_no_ghost(g, 1, j, +1);
+    auto zplane = [&](int k) { return col + (long long)(k + G) * sz; };
+    // z neighbours of Sigma: wrap or self at the ends
+    auto zsig = [&](int k) {
+        if (k < 0) return g.periodic[2] ? nz - 1 : 0;
+        if (k >= nz) return g.periodic[2] ? 0 : nz - 1;
+        return k;
+    };
+    C ir_m = C(1) / S::load(U + zplane(z0 - 1));   // rho ghost plane at the domain ends
+    C ir_c = C(1) / S::load(U + zplane(z0));
+    C s_m = S::load(Sin + col + (long long)(zsig(z0 - 1) + G) * sz);
+    C s_c = S::load(Sin + zplane(z0));
+    C u_m[3], u_c[3];
+    if (FIRST) {
+        for (int c = 0; c < 3; ++c) {
+            u_m[c] = S::load(U + (1 + c) * fs + zplane(z0 - 1)) * ir_m;
+            u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
+        }
+    }
+    for (int k = z0; k < z1; ++k) {
+        const long long o = zplane(k);
+        const long long op = zplane(k + 1);
+        const C ir_p = C(1) / S::load(U + op);
+        const C s_p = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+        C bk;
+        C u_p[3];
+        if (FIRST) {
+            for (int c = 0; c < 3; ++c) u_p[c] = S::load(U + (1 + c) * fs + op) * ir_p;
+            C Gm[3][3];
+            const long long nb[2][2] = {{o - 1, o + 1}, {o - sy, o + sy}};
+            for (int d = 0; d < 2; ++d) {
+                const C irm = C(1) / S::load(U + nb[d][0]);
+                const C irp = C(1) / S::load(U + nb[d][1]);
+                const C sc = C(0.5) * C(g.ih[d]);
+                for (int c = 0; c < 3; ++c)
+                    Gm[c][d] = (S::load(U + (1 + c) * fs + nb[d][1]) * irp - S::load(U + (1 + c) * fs + nb[d][0]) * irm) * sc;
+            }
+            const C scz = C(0.5) * C(g.ih[2]);
+            for (int c = 0; c < 3; ++c) Gm[c][2] = (u_p[c] - u_m[c]) * scz;
+            const C tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
+            C tr2 = C(0);
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
+            bk = alpha * (tr2 + tr * tr);
+            b[o] = bk;
+        } else {
+            bk = b[o];
+        }
+        const C ic = ir_c;
+        const C bxm = half * (ic + C(1) / S::load(U + o - 1));
+        const C bxp = half * (ic + C(1) / S::load(U + o + 1));
+        const C bym = half * (ic + C(1) / S::load(U + o - sy));
+        const C byp = half * (ic + C(1) / S::load(U + o + sy));
+        const C bzm = half * (ic + ir_m);
+        const C bzp = half * (ic + ir_p);
+        C num = bk;
+        C den = ic;
+        num += alpha * (bxp * S::load(Sin + o + oxp) + bxm * S::load(Sin + o + oxm)) * hx2;
+        den += alpha * (bxp + bxm) * hx2;
+        num += alpha * (byp * S::load(Sin + o + oyp) + bym * S::load(Sin + o + oym)) * hy2;
+        den += alpha * (byp + bym) * hy2;
+        num += alpha * (bzp * s_p + bzm * s_m) * hz2;
+        den += alpha * (bzp + bzm) * hz2;
+        S::store(Sout + o, num / den);
+        ir_m = ir_c;
+        ir_c = ir_p;
+        s_m = s_c;
+        s_c = s_p;
+        if (FIRST)
+            for (int c = 0; c < 3; ++c) {
+                u_m[c] = u_c[c];
+                u_c[c] = u_p[c];
+            }
+    }
+}
+
+}  // namespace igr

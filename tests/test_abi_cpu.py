@@ -54,7 +54,7 @@ def _init(grid, gamma, alpha, bc, opts):
 @pytest.mark.parametrize("case,code", [
     ("null", igr.IGR_EINVAL), ("gamma", igr.IGR_EINVAL), ("alpha", igr.IGR_EINVAL), ("extent", igr.IGR_EINVAL),
     ("pair", igr.IGR_EINVAL), ("precision", igr.IGR_EINVAL), ("order", igr.IGR_EUNSUPPORTED),
-    ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("flags", igr.IGR_EUNSUPPORTED),
+    ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("sigma_block", igr.IGR_EINVAL),
 ])
 def test_init_rejects_bad_arguments(case, code):
     grid, bc, opts, gamma, alpha = _grid(), _bc(), igr.Opts(0, 5, 5, 0), 1.4, 0.01
@@ -76,8 +76,8 @@ def test_init_rejects_bad_arguments(case, code):
         opts = igr.Opts(0, 5, -1, 0)
     elif case == "spacing":
         grid = igr.Grid(8, 8, 8, 0.0, 0.1, 0.1)
-    elif case == "flags":
-        opts = igr.Opts(0, 5, 5, 3)
+    elif case == "sigma_block":
+        opts = igr.Opts(0, 5, 5, 9)
     rc, h = _init(grid, gamma, alpha, bc, opts)
     assert rc == code
     assert h.value is None

@@ -59,11 +59,11 @@ def _sigma0(w, seed=7):
     return np.random.default_rng(seed).random((w.nz, w.ny, w.nx)) * 0.1
 
 
-@pytest.mark.parametrize("nsweeps", [0, 1, 5])
-def test_sigma_solve(case, nsweeps):
+@pytest.mark.parametrize("nsweeps,sigma_block", [(0, 1), (1, 1), (5, 1), (5, 2), (5, 5), (7, 3)])
+def test_sigma_solve(case, nsweeps, sigma_block):
     name, w = case
-    banner(f"sigma_solve {name} nsweeps={nsweeps}")
-    s = igr.Solver.from_workload(w)
+    banner(f"sigma_solve {name} nsweeps={nsweeps} sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, sigma_block=sigma_block)
     U = s.state_from(w.U)
     sig = s.field_from(_sigma0(w))
     res = s.sigma_solve(U, sig, nsweeps=nsweeps, residual=True)
@@ -74,10 +74,11 @@ def test_sigma_solve(case, nsweeps):
     assert abs(res - want_res) <= 1e-10 * max(want_res, 1e-300)
 
 
-def test_rhs(case):
+@pytest.mark.parametrize("sigma_block", [1, 5])
+def test_rhs(case, sigma_block):
     name, w = case
-    banner(f"rhs {name}")
-    s = igr.Solver.from_workload(w)
+    banner(f"rhs {name} sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, sigma_block=sigma_block)
     U = s.state_from(w.U)
     sig = s.field_from(_sigma0(w))
     L = s.rhs(U, sig)
