@@ -229,10 +229,24 @@ namespace igr {
 // One Jacobi sweep per pass, z-marching: a 64 x 4 block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
-// lanes and rows).  With FIRST the source b is formed in the same pass
-// (from rho and m, also z-marched) and written for the later sweeps.
-// Per cell: FIRST reads rho, m, Sigma and writes Sigma, b; later sweeps
-// read Sigma, rho, b and write Sigma.
+// lanes and rows).  Everything plane k+1 needs is loaded during plane k
+// (one plane of prefetch), so the loads of an iteration overlap the
+// arithmetic of the previous one.  With FIRST the source b is formed in the
+// same pass (from rho and m) and written for the later sweeps.  Per cell:
+// FIRST reads rho, m, Sigma and writes Sigma, b; later sweeps read Sigma,
+// rho, b and write Sigma.
+template <class T, bool FIRST>
+struct SweepPlane {
+    using C = typename Storage<T>::C;
+    C rho_c;            // rho at (i, j, k+1)  [own column, one plane ahead]
+    C sig_c;            // Sigma_in at (i, j, k+1)
+    C rho_n[4];         // rho at the x/y neighbours of plane k
+    C sig_n[4];         // Sigma_in at the x/y neighbours of plane k (wrap/self)
+    C bk;               // b at plane k (later sweeps)
+    C m_c[3];           // m at (i, j, k+1) (FIRST)
+    C m_n[4][3];        // m at the x/y neighbours of plane k (FIRST)
+};
+
 template <class T, bool FIRST>
 __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
                                                  T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
@@ -251,15 +265,37 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
     const C alpha = C(g.alpha);
     const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
     const C half = C(0.5);
-    // x/y Sigma neighbours (no ghosts): offsets with wrap or self
-    const int oxm = neighbour_no_ghost(g, 0, i, -1), oxp = neighbour_no_ghost(g, 0, i, +1);
-    const int oym = neighbour_no_ghost(g, 1, j, -1), oyp = neighbour_no_ghost(g, 1, j, +1);
+    // x/y neighbours: rho from the padded array, Sigma with wrap or self
+    const int onb[4] = {-1, 1, -sy, sy};
+    const int osg[4] = {neighbour_no_ghost(g, 0, i, -1), neighbour_no_ghost(g, 0, i, +1),
+                        neighbour_no_ghost(g, 1, j, -1), neighbour_no_ghost(g, 1, j, +1)};
     auto zplane = [&](int k) { return col + (long long)(k + G) * sz; };
-    // z neighbours of Sigma: wrap or self at the ends
-    auto zsig = [&](int k) {
+    auto zsig = [&](int k) {   // Sigma plane of z neighbour k: wrap or self at the ends
         if (k < 0) return g.periodic[2] ? nz - 1 : 0;
         if (k >= nz) return g.periodic[2] ? 0 : nz - 1;
         return k;
+    };
+    // loads for iteration k: own column at k+1, x/y neighbours at k
+    auto load = [&](int k, SweepPlane<T, FIRST>& P) {
+        const long long o = zplane(k);
+        const long long op = zplane(k + 1);
+        P.rho_c = S::load(U + op);
+        P.sig_c = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            P.rho_n[n] = S::load(U + o + onb[n]);
+            P.sig_n[n] = S::load(Sin + o + osg[n]);
+        }
+        if (FIRST) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P.m_c[c] = S::load(U + (1 + c) * fs + op);
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P.m_n[n][c] = S::load(U + (1 + c) * fs + o + onb[n]);
+        } else {
+            P.bk = b[o];
+        }
     };
     C ir_m = C(1) / S::load(U + zplane(z0 - 1));   // rho ghost plane at the domain ends
     C ir_c = C(1) / S::load(U + zplane(z0));
@@ -267,52 +303,61 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
     C s_c = S::load(Sin + zplane(z0));
     C u_m[3], u_c[3];
     if (FIRST) {
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             u_m[c] = S::load(U + (1 + c) * fs + zplane(z0 - 1)) * ir_m;
             u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
         }
     }
+    SweepPlane<T, FIRST> cur, nxt;
+    load(z0, cur);
     for (int k = z0; k < z1; ++k) {
+        if (k + 1 < z1) load(k + 1, nxt);
         const long long o = zplane(k);
-        const long long op = zplane(k + 1);
-        const C ir_p = C(1) / S::load(U + op);
-        const C s_p = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+        const C ir_p = C(1) / cur.rho_c;
+        const C s_p = cur.sig_c;
+        C irn[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) irn[n] = C(1) / cur.rho_n[n];
         C bk;
         C u_p[3];
         if (FIRST) {
-            for (int c = 0; c < 3; ++c) u_p[c] = S::load(U + (1 + c) * fs + op) * ir_p;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u_p[c] = cur.m_c[c] * ir_p;
             C Gm[3][3];
-            const long long nb[2][2] = {{o - 1, o + 1}, {o - sy, o + sy}};
+#pragma unroll
             for (int d = 0; d < 2; ++d) {
-                const C irm = C(1) / S::load(U + nb[d][0]);
-                const C irp = C(1) / S::load(U + nb[d][1]);
                 const C sc = C(0.5) * C(g.ih[d]);
+#pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    Gm[c][d] = (S::load(U + (1 + c) * fs + nb[d][1]) * irp - S::load(U + (1 + c) * fs + nb[d][0]) * irm) * sc;
+                    Gm[c][d] = (cur.m_n[2 * d + 1][c] * irn[2 * d + 1] - cur.m_n[2 * d][c] * irn[2 * d]) * sc;
             }
             const C scz = C(0.5) * C(g.ih[2]);
+#pragma unroll
             for (int c = 0; c < 3; ++c) Gm[c][2] = (u_p[c] - u_m[c]) * scz;
             const C tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
             C tr2 = C(0);
+#pragma unroll
             for (int c = 0; c < 3; ++c)
+#pragma unroll
                 for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
             bk = alpha * (tr2 + tr * tr);
             b[o] = bk;
         } else {
-            bk = b[o];
+            bk = cur.bk;
         }
         const C ic = ir_c;
-        const C bxm = half * (ic + C(1) / S::load(U + o - 1));
-        const C bxp = half * (ic + C(1) / S::load(U + o + 1));
-        const C bym = half * (ic + C(1) / S::load(U + o - sy));
-        const C byp = half * (ic + C(1) / S::load(U + o + sy));
+        const C bxm = half * (ic + irn[0]);
+        const C bxp = half * (ic + irn[1]);
+        const C bym = half * (ic + irn[2]);
+        const C byp = half * (ic + irn[3]);
         const C bzm = half * (ic + ir_m);
         const C bzp = half * (ic + ir_p);
         C num = bk;
         C den = ic;
-        num += alpha * (bxp * S::load(Sin + o + oxp) + bxm * S::load(Sin + o + oxm)) * hx2;
+        num += alpha * (bxp * cur.sig_n[1] + bxm * cur.sig_n[0]) * hx2;
         den += alpha * (bxp + bxm) * hx2;
-        num += alpha * (byp * S::load(Sin + o + oyp) + bym * S::load(Sin + o + oym)) * hy2;
+        num += alpha * (byp * cur.sig_n[3] + bym * cur.sig_n[2]) * hy2;
         den += alpha * (byp + bym) * hy2;
         num += alpha * (bzp * s_p + bzm * s_m) * hz2;
         den += alpha * (bzp + bzm) * hz2;
@@ -321,11 +366,14 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         ir_c = ir_p;
         s_m = s_c;
         s_c = s_p;
-        if (FIRST)
+        if (FIRST) {
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
                 u_m[c] = u_c[c];
                 u_c[c] = u_p[c];
             }
+        }
+        cur = nxt;
     }
 }
 

@@ -151,23 +151,28 @@ def _plane_loss(s, w, dt, i0):
     return loss
 
 
-@pytest.mark.parametrize("plane", ["x=0.75L", "x=12dx"])
+@pytest.mark.parametrize("plane", ["x=0.75L", "x=4dx"])
 def test_gradient_workload_128_against_finite_differences(plane):
     """At x = 0.75 L (the specified plane) no signal from the inlet arrives
-    within 40 steps (at most ~0.3 cells per step travel), so dJ/dp_jet is
-    exactly zero in both the adjoint and the finite differences; the plane
-    at 12 cells is reached and gives nonzero jet-pressure derivatives."""
+    within 40 steps (at most ~0.3 cells per step), and with u = 0 there a
+    density perturbation leaves p unchanged, so dJ/dp_jet and dJ/drho0 are
+    zero in exact arithmetic: the finite differences give exactly 0 and the
+    adjoint gives round-off.  The plane at 4 cells lies in the jets' initial
+    plug, where both derivatives are far above the h = 1e-6 noise floor
+    (about 1e-16 J / h), and adjoint and central differences must agree to
+    1e-6 relative."""
     w = inputs.gradient_jets(128)
     banner(f"gradient workload 128^3: 40 steps, checkpoints every 10, FD h=1e-6, plane {plane}")
     s = igr.Solver.from_workload(w)
     dt = w.dt_fixed
-    i0 = int(0.75 * w.nx) if plane == "x=0.75L" else 12
+    i0 = int(0.75 * w.nx) if plane == "x=0.75L" else 4
     loss_fn = _plane_loss(s, w, dt, i0)
     U0 = s.state_from(w.U).requires_grad_(True)
     S0 = s.new_field()
     p = torch.tensor([j.p for j in w.jets], dtype=torch.float64, requires_grad=True)
     J, _, _ = run_checkpointed(s, U0, S0, p, dt, w.nsteps, loss_fn, every=10)
     J.backward()
+    Jv = float(J)
     gp = p.grad.clone()
     gU = U0.grad.detach().clone()
 
@@ -201,8 +206,11 @@ def test_gradient_workload_128_against_finite_differences(plane):
     v[0] = rng.standard_normal(w.U.shape[1:])
     fd = (J_of(base, w.U + h * v) - J_of(base, w.U - h * v)) / (2 * h)
     ad = float((Solver_interior(gU) * torch.from_numpy(v).to(gU.device)).sum())
-    print(f"[gpu-case] {plane} dJ/drho0 . v: adjoint {ad:.12e} fd {fd:.12e}", flush=True)
-    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    print(f"[gpu-case] {plane} dJ/drho0 . v: adjoint {ad:.12e} fd {fd:.12e} (J = {Jv:.6e})", flush=True)
+    if plane == "x=0.75L":
+        assert fd == 0.0 and abs(ad) <= 1e-12 * Jv
+    else:
+        assert abs(ad - fd) <= 1e-6 * abs(fd)
 
 
 def Solver_interior(a):
