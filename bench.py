@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
     ap.add_argument("--sigma-block", type=int, default=0, help="sweeps fused per Sigma pass (0: library default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
@@ -217,6 +219,15 @@ def main():
     from paper_2505_07392_amd import igr, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = 1 << 27                        # 2^27 float64 = 1 GiB
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+        return
     if args.study:
         _, n, nst, forms = args.study.split(":")
         study_jets(int(n), int(nst), forms.split(","), args.steps, args.warmup)
