@@ -225,25 +225,29 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 // of the temporally blocked kernel.  The last iterate ends in `sig` (device
 // copy after an odd number of passes) and its ghosts are filled.
 template <class T>
-int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
+int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, hipStream_t s) {
     using C = typename Storage<T>::C;
-    T* src = sig;
-    T* dst = static_cast<T*>(c->d_sig2);
+    T* src = in;
+    T* dst = other;
     if (c->sigma_block <= 1) {
         const Geom& g = c->g;
-        const long long tiles = (long long)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4);
+        const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + 3) / 4;
+        const long long tiles = (long long)tiles_x * tiles_y;
         long long zc = (tiles * g.n[2] + 2047) / 2048;
         if (zc < 4) zc = 4;
         if (zc > 64) zc = 64;
         if (zc > g.n[2]) zc = g.n[2];
-        const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, unsigned((g.n[2] + zc - 1) / zc));
+        const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
+        if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
         C* b = static_cast<C*>(c->d_b);
         for (int it = 0; it < nsweeps; ++it) {
             IGR_TRY(launch(c, K_JACOBI, s, [&] {
                 if (it == 0)
-                    k_sweep_z<T, true><<<grid, dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc));
+                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc),
+                                                                                      tiles_x, tiles_y);
                 else
-                    k_sweep_z<T, false><<<grid, dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc));
+                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc),
+                                                                                       tiles_x, tiles_y);
             }));
             T* tmp = src;
             src = dst;
@@ -261,8 +265,17 @@ int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
             dst = tmp;
         }
     }
-    if (src != sig) IGR_HIP(hipMemcpyAsync(sig, src, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
-    return fill_sigma_ghosts(c, sig, s);
+    *result = src;
+    return fill_sigma_ghosts(c, src, s);
+}
+
+// As sigma_solve_buf, with the result always in `sig`.
+template <class T>
+int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
+    T* res = nullptr;
+    IGR_TRY(sigma_solve_buf(c, U, sig, static_cast<T*>(c->d_sig2), nsweeps, &res, s));
+    if (res != sig) IGR_HIP(hipMemcpyAsync(sig, res, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
+    return IGR_OK;
 }
 
 // Source b into the scratch array (for the residual diagnostic).
@@ -296,8 +309,9 @@ FluxLaunch flux_launch(const Geom& g, int ty) {
     L.tiles_x = (g.n[0] + FLUX_TX - 1) / FLUX_TX;
     L.tiles_y = (g.n[1] + ty - 1) / ty;
     const long long tiles = (long long)L.tiles_x * L.tiles_y;
-    long long zc = (tiles * g.n[2] + 2047) / 2048;
-    if (zc < 4) zc = 4;
+    // long chunks: every chunk re-reads five planes to prime its z queue
+    long long zc = (tiles * g.n[2] + 1023) / 1024;
+    if (zc < 8) zc = 8;
     if (zc > 64) zc = 64;
     if (zc > g.n[2]) zc = g.n[2];
     L.zc = int(zc);
@@ -354,18 +368,32 @@ int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t
     }
     T* Ua = static_cast<T*>(c->d_Ua);
     T* Ub = static_cast<T*>(c->d_Ub);
+    // Sigma ping-pongs between the caller's buffer and the scratch copy
+    // across the three stages; one copy at the end if it ends in scratch
+    T* cur = sig;
+    T* oth = static_cast<T*>(c->d_sig2);
+    auto solve = [&](T* Us) -> int {
+        T* res = nullptr;
+        IGR_TRY(sigma_solve_buf(c, Us, cur, oth, c->nsweeps, &res, s));
+        if (res != cur) {
+            oth = cur;
+            cur = res;
+        }
+        return IGR_OK;
+    };
     // stage 1: U1 = Un + dt L(Un)
     IGR_TRY(fill_state_ghosts(c, U, s));
-    IGR_TRY(sigma_solve_impl(c, U, sig, c->nsweeps, s));
-    IGR_TRY((flux_impl<T, MODE_STAGE1>(c, U, sig, nullptr, Ua, dtp, dt_fixed, s)));
+    IGR_TRY(solve(U));
+    IGR_TRY((flux_impl<T, MODE_STAGE1>(c, U, cur, nullptr, Ua, dtp, dt_fixed, s)));
     // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
     IGR_TRY(fill_state_ghosts(c, Ua, s));
-    IGR_TRY(sigma_solve_impl(c, Ua, sig, c->nsweeps, s));
-    IGR_TRY((flux_impl<T, MODE_STAGE2>(c, Ua, sig, U, Ub, dtp, dt_fixed, s)));
+    IGR_TRY(solve(Ua));
+    IGR_TRY((flux_impl<T, MODE_STAGE2>(c, Ua, cur, U, Ub, dtp, dt_fixed, s)));
     // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un
     IGR_TRY(fill_state_ghosts(c, Ub, s));
-    IGR_TRY(sigma_solve_impl(c, Ub, sig, c->nsweeps, s));
-    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, sig, U, U, dtp, dt_fixed, s)));
+    IGR_TRY(solve(Ub));
+    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s)));
+    if (cur != sig) IGR_HIP(hipMemcpyAsync(sig, cur, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
     return IGR_OK;
 }
 

@@ -174,8 +174,8 @@ __device__ __forceinline__ C recon_right(C b, C c, C d, C e, C f) {
 template <class C>
 __device__ __forceinline__ void llf_flux(const C UL[5], const C UR[5], C SL, C SR, int d, C gamma,
                                          C F[5], bool& bad) {
-    const C irl = C(1) / UL[0];
-    const C irr = C(1) / UR[0];
+    const C irl = fast_rcp(UL[0]);
+    const C irr = fast_rcp(UR[0]);
     const C pl = (gamma - C(1)) * (UL[4] - C(0.5) * (UL[1] * UL[1] + UL[2] * UL[2] + UL[3] * UL[3]) * irl);
     const C pr = (gamma - C(1)) * (UR[4] - C(0.5) * (UR[1] * UR[1] + UR[2] * UR[2] + UR[3] * UR[3]) * irr);
     bad |= !(UL[0] > C(0)) | !(UR[0] > C(0)) | !(pl > C(0)) | !(pr > C(0));

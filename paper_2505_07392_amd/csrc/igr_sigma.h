@@ -250,12 +250,26 @@ struct SweepPlane {
 template <class T, bool FIRST>
 __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
                                                  T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
-                                                 Geom g, int zc) {
+                                                 Geom g, int zc, int tiles_x, int tiles_y) {
     using S = Storage<T>;
     using C = typename S::C;
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int z0 = blockIdx.z * zc;
+    // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
+    // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
+    // tiles are fetched once into that XCD's L2
+    int bidx = blockIdx.x;
+    {
+        constexpr int NXCD = 8;
+        const int nb = gridDim.x;
+        const int full = nb - nb % NXCD;
+        if (bidx < full) bidx = (bidx % NXCD) * (full / NXCD) + bidx / NXCD;
+    }
+    const int bx = bidx % tiles_x;
+    bidx /= tiles_x;
+    const int by = bidx % tiles_y;
+    const int bz = bidx / tiles_y;
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * 4 + threadIdx.y;
+    const int z0 = bz * zc;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     if (i >= nx || j >= ny) return;
     const int z1 = min(z0 + zc, nz);
@@ -314,11 +328,11 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
     for (int k = z0; k < z1; ++k) {
         if (k + 1 < z1) load(k + 1, nxt);
         const long long o = zplane(k);
-        const C ir_p = C(1) / cur.rho_c;
+        const C ir_p = fast_rcp(cur.rho_c);
         const C s_p = cur.sig_c;
         C irn[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) irn[n] = C(1) / cur.rho_n[n];
+        for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(cur.rho_n[n]);
         C bk;
         C u_p[3];
         if (FIRST) {
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         den += alpha * (byp + bym) * hy2;
         num += alpha * (bzp * s_p + bzm * s_m) * hz2;
         den += alpha * (bzp + bzm) * hz2;
-        S::store(Sout + o, num / den);
+        S::store(Sout + o, num * fast_rcp(den));
         ir_m = ir_c;
         ir_c = ir_p;
         s_m = s_c;
