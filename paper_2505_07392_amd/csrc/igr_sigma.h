@@ -229,22 +229,26 @@ namespace igr {
 // One Jacobi sweep per pass, z-marching: a 64 x 4 block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
-// lanes and rows).  Everything plane k+1 needs is loaded during plane k
-// (one plane of prefetch), so the loads of an iteration overlap the
-// arithmetic of the previous one.  With FIRST the source b is formed in the
-// same pass (from rho and m) and written for the later sweeps.  Per cell:
-// FIRST reads rho, m, Sigma and writes Sigma, b; later sweeps read Sigma,
-// rho, b and write Sigma.
+// lanes and rows).  Loads are issued ahead of use (see SweepCol) so that
+// enough bytes are in flight per CU to cover HBM latency.  With FIRST the
+// source b is formed in the same pass (from rho and m) and written for the
+// later sweeps.  Per cell: FIRST reads rho, m, Sigma and writes Sigma, b;
+// later sweeps read Sigma, rho, b and write Sigma.
+// Loads of one iteration of the single-sweep kernel.  The own-column values
+// of plane k+1 (which miss to HBM) are fetched PD iterations ahead; the x/y
+// neighbours of plane k (mostly L1/L2 hits: other threads' columns) one
+// iteration ahead.
 template <class T, bool FIRST>
-struct SweepPlane {
+struct SweepCol {
     using C = typename Storage<T>::C;
-    C rho_c;            // rho at (i, j, k+1)  [own column, one plane ahead]
-    C sig_c;            // Sigma_in at (i, j, k+1)
-    C rho_n[4];         // rho at the x/y neighbours of plane k
-    C sig_n[4];         // Sigma_in at the x/y neighbours of plane k (wrap/self)
-    C bk;               // b at plane k (later sweeps)
-    C m_c[3];           // m at (i, j, k+1) (FIRST)
-    C m_n[4][3];        // m at the x/y neighbours of plane k (FIRST)
+    C rho, sig, b;      // rho, Sigma_in at plane k+1; b at plane k (later sweeps)
+    C m[3];             // m at plane k+1 (FIRST)
+};
+template <class T, bool FIRST>
+struct SweepNb {
+    using C = typename Storage<T>::C;
+    C rho[4], sig[4];   // x/y neighbours of plane k
+    C m[4][3];          // (FIRST)
 };
 
 template <class T, bool FIRST>
@@ -253,6 +257,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
                                                  Geom g, int zc, int tiles_x, int tiles_y) {
     using S = Storage<T>;
     using C = typename S::C;
+    constexpr int PD = 3;   // own-column prefetch distance (planes)
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
     // tiles are fetched once into that XCD's L2
@@ -289,30 +294,33 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         if (k >= nz) return g.periodic[2] ? 0 : nz - 1;
         return k;
     };
-    // loads for iteration k: own column at k+1, x/y neighbours at k
-    auto load = [&](int k, SweepPlane<T, FIRST>& P) {
-        const long long o = zplane(k);
+    auto load_col = [&](int k, SweepCol<T, FIRST>& P) {   // for iteration k
         const long long op = zplane(k + 1);
-        P.rho_c = S::load(U + op);
-        P.sig_c = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+        P.rho = S::load(U + op);
+        P.sig = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+        if (FIRST) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P.m[c] = S::load(U + (1 + c) * fs + op);
+        } else {
+            P.b = b[zplane(k)];
+        }
+    };
+    auto load_nb = [&](int k, SweepNb<T, FIRST>& P) {
+        const long long o = zplane(k);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            P.rho_n[n] = S::load(U + o + onb[n]);
-            P.sig_n[n] = S::load(Sin + o + osg[n]);
+            P.rho[n] = S::load(U + o + onb[n]);
+            P.sig[n] = S::load(Sin + o + osg[n]);
         }
         if (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) P.m_c[c] = S::load(U + (1 + c) * fs + op);
-#pragma unroll
             for (int n = 0; n < 4; ++n)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) P.m_n[n][c] = S::load(U + (1 + c) * fs + o + onb[n]);
-        } else {
-            P.bk = b[o];
+                for (int c = 0; c < 3; ++c) P.m[n][c] = S::load(U + (1 + c) * fs + o + onb[n]);
         }
     };
-    C ir_m = C(1) / S::load(U + zplane(z0 - 1));   // rho ghost plane at the domain ends
-    C ir_c = C(1) / S::load(U + zplane(z0));
+    C ir_m = fast_rcp(S::load(U + zplane(z0 - 1)));   // rho ghost plane at the domain ends
+    C ir_c = fast_rcp(S::load(U + zplane(z0)));
     C s_m = S::load(Sin + col + (long long)(zsig(z0 - 1) + G) * sz);
     C s_c = S::load(Sin + zplane(z0));
     C u_m[3], u_c[3];
@@ -323,28 +331,36 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
             u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
         }
     }
-    SweepPlane<T, FIRST> cur, nxt;
-    load(z0, cur);
+    SweepCol<T, FIRST> q[PD];   // own columns for iterations k .. k+PD-1
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+        if (z0 + d < z1) load_col(z0 + d, q[d]);
+    SweepNb<T, FIRST> cur, nxt;
+    load_nb(z0, cur);
     for (int k = z0; k < z1; ++k) {
-        if (k + 1 < z1) load(k + 1, nxt);
+        const SweepCol<T, FIRST> cc = q[0];
+#pragma unroll
+        for (int d = 0; d < PD - 1; ++d) q[d] = q[d + 1];
+        if (k + PD < z1) load_col(k + PD, q[PD - 1]);
+        if (k + 1 < z1) load_nb(k + 1, nxt);
         const long long o = zplane(k);
-        const C ir_p = fast_rcp(cur.rho_c);
-        const C s_p = cur.sig_c;
+        const C ir_p = fast_rcp(cc.rho);
+        const C s_p = cc.sig;
         C irn[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(cur.rho_n[n]);
+        for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(cur.rho[n]);
         C bk;
         C u_p[3];
         if (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) u_p[c] = cur.m_c[c] * ir_p;
+            for (int c = 0; c < 3; ++c) u_p[c] = cc.m[c] * ir_p;
             C Gm[3][3];
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const C sc = C(0.5) * C(g.ih[d]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    Gm[c][d] = (cur.m_n[2 * d + 1][c] * irn[2 * d + 1] - cur.m_n[2 * d][c] * irn[2 * d]) * sc;
+                    Gm[c][d] = (cur.m[2 * d + 1][c] * irn[2 * d + 1] - cur.m[2 * d][c] * irn[2 * d]) * sc;
             }
             const C scz = C(0.5) * C(g.ih[2]);
 #pragma unroll
@@ -358,7 +374,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
             bk = alpha * (tr2 + tr * tr);
             b[o] = bk;
         } else {
-            bk = cur.bk;
+            bk = cc.b;
         }
         const C ic = ir_c;
         const C bxm = half * (ic + irn[0]);
@@ -369,9 +385,9 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         const C bzp = half * (ic + ir_p);
         C num = bk;
         C den = ic;
-        num += alpha * (bxp * cur.sig_n[1] + bxm * cur.sig_n[0]) * hx2;
+        num += alpha * (bxp * cur.sig[1] + bxm * cur.sig[0]) * hx2;
         den += alpha * (bxp + bxm) * hx2;
-        num += alpha * (byp * cur.sig_n[3] + bym * cur.sig_n[2]) * hy2;
+        num += alpha * (byp * cur.sig[3] + bym * cur.sig[2]) * hy2;
         den += alpha * (byp + bym) * hy2;
         num += alpha * (bzp * s_p + bzm * s_m) * hz2;
         den += alpha * (bzp + bzm) * hz2;
