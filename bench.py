@@ -223,10 +223,15 @@ def main():
         n = 1 << 27                        # 2^27 float64 = 1 GiB
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+        el = (time.perf_counter() - t0) / 3
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 4,
+                          "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
     if args.study:
         _, n, nst, forms = args.study.split(":")

@@ -233,8 +233,14 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         const Geom& g = c->g;
         const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + 3) / 4;
         const long long tiles = (long long)tiles_x * tiles_y;
-        long long zc = (tiles * g.n[2] + 2047) / 2048;
-        if (zc < 4) zc = 4;
+#ifndef IGR_SWEEP_BLOCKS
+#define IGR_SWEEP_BLOCKS 2048
+#endif
+#ifndef IGR_SWEEP_ZC_MIN
+#define IGR_SWEEP_ZC_MIN 4
+#endif
+        long long zc = (tiles * g.n[2] + IGR_SWEEP_BLOCKS - 1) / IGR_SWEEP_BLOCKS;
+        if (zc < IGR_SWEEP_ZC_MIN) zc = IGR_SWEEP_ZC_MIN;
         if (zc > 64) zc = 64;
         if (zc > g.n[2]) zc = g.n[2];
         const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
@@ -290,13 +296,29 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 // sized for >= ~2048 blocks (256 CUs, several resident blocks each).
 // Rows per tile: the block (TY+1 waves) must fill the waves one CU can
 // hold at the kernel's register use (FP64: 8 per CU, FP32: 12).
+// (measured on the 256^3 box: FP64 TY = 7 with ~2048 blocks, FP32
+// arithmetic TY = 11 with ~512 blocks; TY = 3..5 is 20-75 % slower)
+#ifndef IGR_FLUX_TY_F64
+#define IGR_FLUX_TY_F64 7
+#endif
+#ifndef IGR_FLUX_TY_F32
+#define IGR_FLUX_TY_F32 11
+#endif
+#ifndef IGR_FLUX_BLOCKS_F64
+#define IGR_FLUX_BLOCKS_F64 2048
+#endif
+#ifndef IGR_FLUX_BLOCKS_F32
+#define IGR_FLUX_BLOCKS_F32 512
+#endif
 template <class T>
 struct FluxShape {
-    static constexpr int TY = 5;
+    static constexpr int TY = IGR_FLUX_TY_F32;
+    static constexpr int BLOCKS = IGR_FLUX_BLOCKS_F32;
 };
 template <>
 struct FluxShape<double> {
-    static constexpr int TY = 7;
+    static constexpr int TY = IGR_FLUX_TY_F64;
+    static constexpr int BLOCKS = IGR_FLUX_BLOCKS_F64;
 };
 
 struct FluxLaunch {
@@ -304,13 +326,13 @@ struct FluxLaunch {
     long long blocks() const { return (long long)tiles_x * tiles_y * chunks; }
 };
 
-FluxLaunch flux_launch(const Geom& g, int ty) {
+FluxLaunch flux_launch(const Geom& g, int ty, int target_blocks) {
     FluxLaunch L;
     L.tiles_x = (g.n[0] + FLUX_TX - 1) / FLUX_TX;
     L.tiles_y = (g.n[1] + ty - 1) / ty;
     const long long tiles = (long long)L.tiles_x * L.tiles_y;
     // long chunks: every chunk re-reads five planes to prime its z queue
-    long long zc = (tiles * g.n[2] + 1023) / 1024;
+    long long zc = (tiles * g.n[2] + target_blocks - 1) / target_blocks;
     if (zc < 8) zc = 8;
     if (zc > 64) zc = 64;
     if (zc > g.n[2]) zc = g.n[2];
@@ -323,7 +345,7 @@ template <class T, int MODE>
 int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
               hipStream_t s) {
     constexpr int TY = FluxShape<T>::TY;
-    const FluxLaunch L = flux_launch(c->g, TY);
+    const FluxLaunch L = flux_launch(c->g, TY, FluxShape<T>::BLOCKS);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
         k_flux_tiled<T, MODE, TY><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
