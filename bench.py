@@ -119,40 +119,38 @@ def run_form(w, precision, steps, warmup, sigma_block=0):
 def jet_workload(n: int, nsteps: int):
     from paper_2505_07392_amd import inputs
 
-    w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10, nsteps=nsteps)
+    w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10, nsteps=nsteps,
+                         build_state=False)
     w.alpha = 4.0 * w.dx * w.dx     # Mach-3 jets need alpha = 4 dx^2 (alpha = dx^2 loses positivity)
     return w
 
 
-def rel_l1(a, b):
-    import torch
-
-    return [float((a[f] - b[f]).abs().sum() / b[f].abs().sum()) if float(b[f].abs().sum()) > 0 else 0.0
-            for f in range(a.shape[0])]
-
-
 def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
-    """Multi-jet box: rate of each precision form, footprint, and per-field
-    rel L1 error of FP32 / BF16 against the FP64 run after `nsteps` steps
-    with the same fixed dt."""
+    """Multi-jet box: rate of each precision form, device memory in use, and
+    per-field rel L1 error of the other forms against the FP64 run after
+    `nsteps` steps with the same fixed dt (computed on the GPU)."""
     import torch
 
-    from paper_2505_07392_amd import igr
+    from paper_2505_07392_amd import igr, inputs
 
     w = jet_workload(n, nsteps)
     out = {"workload": f"multi_jet_{n}", "cells": w.cells, "steps": nsteps, "alpha_dx2": 4.0, "sweeps": w.nsweeps,
            "forms": {}}
-    finals = {}
+    ref = None
+    dt = None
+    names = ["rho", "mx", "my", "mz", "E", "Sigma"]
     for prec in forms:
-        print(f"[bench] multi-jet {n}^3 {prec}", file=sys.stderr, flush=True)
-        torch.cuda.reset_peak_memory_stats()
-        base = torch.cuda.memory_allocated()
+        print(f"[bench] multi-jet {n}^3 {prec}: building the state", file=sys.stderr, flush=True)
         s = igr.Solver.from_workload(w, precision=prec)
-        U = s.state_from(w.U)
+        U = s.new_state()
+        inputs.fill_multi_jet_state(w, s.interior(U))
+        U0 = U.clone() if nsteps > 0 else None
         S = s.new_field()
-        dt = 0.8 * s.compute_dt(U, w.cfl) if "dt" not in out else out["dt"]
-        out.setdefault("dt", dt)
+        if dt is None:
+            dt = 0.8 * s.compute_dt(U, w.cfl)
+            out["dt"] = dt
         free, total = torch.cuda.mem_get_info()
+        print(f"[bench] multi-jet {n}^3 {prec}: timing", file=sys.stderr, flush=True)
         for _ in range(warmup):
             s.step(U, S, dt_fixed=dt, sync=False)
         torch.cuda.synchronize()
@@ -175,23 +173,35 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
                 ab = algorithmic_bytes_per_cell(k, esz, csz, w.nsweeps) * w.cells
                 form[k] = {"avg_ms": ms / cnt, "achieved_GBs": ab / (ms / cnt / 1e3) / 1e9,
                            "frac": ab / (ms / cnt / 1e3) / 1e9 / HBM_PEAK_GBS}
-        # full-length run from the initial state for the error table
         if nsteps > 0:
-            U = s.state_from(w.U)
-            S = s.new_field()
-            for _ in range(nsteps):
-                s.step(U, S, dt_fixed=dt, sync=False)
-            s.check()
-            finals[prec] = torch.cat([s.interior(U).double(), s.interior(S).double()[None]]).cpu()
+            print(f"[bench] multi-jet {n}^3 {prec}: {nsteps}-step run", file=sys.stderr, flush=True)
+            U.copy_(U0)
+            del U0
+            S.zero_()
+            try:
+                for it in range(nsteps):
+                    s.step(U, S, dt_fixed=dt, sync=False)
+                    if it % 50 == 49:
+                        s.check()
+                        print(f"[bench]   step {it + 1}", file=sys.stderr, flush=True)
+                s.check()
+            except igr.NonFiniteError as e:
+                form["run_failed"] = f"non-physical state reported by step {it + 1}: {e}"
+                out["forms"][prec] = form
+                s.close()
+                continue
+            fin = torch.cat([s.interior(U).double(), s.interior(S).double()[None]])
+            if prec == "f64":
+                ref = fin
+            elif ref is not None:
+                err = [float((fin[f] - ref[f]).abs().sum() / ref[f].abs().sum()) if float(ref[f].abs().sum()) > 0
+                       else 0.0 for f in range(6)]
+                form["rel_l1_vs_f64"] = dict(zip(names, err))
+            del fin
         out["forms"][prec] = form
         del U, S
         s.close()
         torch.cuda.empty_cache()
-    if "f64" in finals:
-        for prec in finals:
-            if prec != "f64":
-                out["forms"][prec]["rel_l1_vs_f64"] = dict(zip(["rho", "mx", "my", "mz", "E", "Sigma"],
-                                                               rel_l1(finals[prec], finals["f64"])))
     print(json.dumps(out), flush=True)
 
 

@@ -189,14 +189,16 @@ def multi_jet(n: int = 512, jets_per_side: int = 4, radius_cells: float = 10.0,
               nsweeps: int = 10, nsteps: int = 200, nx: Optional[int] = None,
               dt_fixed: Optional[float] = None, edge_cells: float = 2.0,
               plug_cells: float = 12.0, front_cells: Optional[float] = 6.0,
-              name: str = "multi_jet") -> Workload:
+              name: str = "multi_jet", build_state: bool = True) -> Workload:
     """Array of supersonic inflow discs into a quiescent box (unit y/z extent).
 
     Each disc edge is a tanh profile of width ``edge_cells``; the initial
     state carries a plug of jet fluid in front of every disc (tanh front at
     ``plug_cells`` from the inlet, width ``front_cells``), so that neither
     the disc edge nor the inlet starts as a jump that the unlimited
-    fifth-order reconstruction would turn into negative face pressures."""
+    fifth-order reconstruction would turn into negative face pressures.
+    With ``build_state=False`` the state is left out (``U is None``); fill a
+    device array plane by plane with :func:`fill_multi_jet_state`."""
     ny = nz = n
     nx = n if nx is None else nx
     dx = 1.0 / n
@@ -211,21 +213,44 @@ def multi_jet(n: int = 512, jets_per_side: int = 4, radius_cells: float = 10.0,
             jets.append(Jet(yc=(a + 0.5) / jets_per_side, zc=(b + 0.5) / jets_per_side,
                             r=radius_cells * dx, rho=rho_j, ux=u0 * factor, uy=0.0, uz=0.0,
                             p=p_j, width=width))
-    owner, chi_r = _jet_blend(ny, nz, dx, jets)
+    w = Workload(name, nx, ny, nz, dx, dx, dx, None, alpha=dx * dx,
+                 faces=(EXTRAP,) * 6, jets=jets, nsweeps=nsweeps, nsteps=nsteps,
+                 dt_fixed=dt_fixed, seed=seed)
+    w.plug = (plug_cells * dx, (edge_cells if front_cells is None else front_cells) * dx)
+    if build_state:
+        owner, chi_r = _jet_blend(ny, nz, dx, jets)
+        chi_x = _plug_profile(nx, dx, *w.plug)
+        chi = chi_r[:, :, None] * chi_x[None, None, :]
+        amb = conserved(np.ones((nz, ny, nx)), 0.0, 0.0, 0.0, 1.0)
+        jet_state = np.stack([conserved(j.rho, j.ux, j.uy, j.uz, j.p) for j in jets])  # [J, 5]
+        Uj = np.moveaxis(jet_state[owner], -1, 0)[:, :, :, None]          # [5, nz, ny, 1]
+        w.U = np.ascontiguousarray((1.0 - chi)[None] * amb + chi[None] * Uj)
+    return w
+
+
+def _plug_profile(nx: int, dx: float, plug: float, front: float) -> np.ndarray:
     x = (np.arange(nx) + 0.5) * dx
-    front = (edge_cells if front_cells is None else front_cells) * dx
     if front > 0:
-        chi_x = 0.5 * (1.0 - np.tanh((x - plug_cells * dx) / front))
-    else:
-        chi_x = (x <= plug_cells * dx).astype(np.float64)
-    chi = chi_r[:, :, None] * chi_x[None, None, :]
-    amb = conserved(np.ones((nz, ny, nx)), 0.0, 0.0, 0.0, 1.0)
-    jet_state = np.stack([conserved(j.rho, j.ux, j.uy, j.uz, j.p) for j in jets])  # [J, 5]
-    Uj = np.moveaxis(jet_state[owner], -1, 0)[:, :, :, None]          # [5, nz, ny, 1]
-    U = np.ascontiguousarray((1.0 - chi)[None] * amb + chi[None] * Uj)
-    return Workload(name, nx, ny, nz, dx, dx, dx, U, alpha=dx * dx,
-                    faces=(EXTRAP,) * 6, jets=jets, nsweeps=nsweeps, nsteps=nsteps,
-                    dt_fixed=dt_fixed, seed=seed)
+        return 0.5 * (1.0 - np.tanh((x - plug) / front))
+    return (x <= plug).astype(np.float64)
+
+
+def fill_multi_jet_state(w: Workload, out) -> None:
+    """Write the multi-jet initial state (same definition as multi_jet's U)
+    into ``out``, a torch tensor view [5, nz, ny, nx] on any device and of
+    any dtype, one z plane at a time (for grids too large to build on the
+    host)."""
+    import torch
+
+    owner, chi_r = _jet_blend(w.ny, w.nz, w.dx, w.jets)
+    chi_x = torch.as_tensor(_plug_profile(w.nx, w.dx, *w.plug), device=out.device)
+    amb = torch.as_tensor(conserved(1.0, 0.0, 0.0, 0.0, 1.0), device=out.device).reshape(5, 1, 1)
+    jet_state = torch.as_tensor(np.stack([conserved(j.rho, j.ux, j.uy, j.uz, j.p) for j in w.jets]),
+                                device=out.device)                                    # [J, 5]
+    for k in range(w.nz):
+        chi = torch.as_tensor(chi_r[k], device=out.device)[:, None] * chi_x[None, :]   # [ny, nx]
+        Uj = jet_state[torch.as_tensor(owner[k], device=out.device)].T[:, :, None]    # [5, ny, 1]
+        out[:, k].copy_(((1.0 - chi)[None] * amb + chi[None] * Uj).to(out.dtype))
 
 
 def gradient_jets(n: int = 128) -> Workload:
