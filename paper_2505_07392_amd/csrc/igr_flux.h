@@ -91,10 +91,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     C q[6][6];
     C Fz_prev[5];
     bool bad = false;
+    // columns that are never loaded keep a valid state (their faces are
+    // evaluated but discarded)
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
-        for (int p = 0; p < 6; ++p) q[f][p] = C(0);
+        for (int p = 0; p < 6; ++p) q[f][p] = f == 0 ? C(1) : (f == 4 ? C(2.5) : C(0));
 #pragma unroll
     for (int f = 0; f < 5; ++f) Fz_prev[f] = C(0);
 
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     // face z0 - 1/2 with the same code as every other z face.
     C nxt[6];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) nxt[f] = C(0);
+    for (int f = 0; f < 6; ++f) nxt[f] = f == 0 ? C(1) : (f == 4 ? C(2.5) : C(0));
     if (col_load) {
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
@@ -186,45 +188,82 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
-            // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv; wave TY,
-            // lanes < TY: face x0-1/2 of row `lane`.  One code path.
-            {
-                const int r = own ? wv : lane;
-                const int fi = own ? lane + 1 : 0;       // face index: face (x0 + fi - 1/2)
-                const int gxf = x0 + fi - 1;             // cell left of the face
-                const bool act = (own || lane < TY) && (y0 + r) < ny && gxf >= -1 && gxf < nx;
-                if (act) {
-                    C v[6][6];
+            if constexpr (sizeof(C) != 4) {
+                // FP64: faces one after the other (register budget)
+                // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv;
+                // wave TY, lanes < TY: face x0-1/2 of row `lane`.  One code path.
+                {
+                    const int r = own ? wv : lane;
+                    const int fi = own ? lane + 1 : 0;       // face index: face (x0 + fi - 1/2)
+                    const int gxf = x0 + fi - 1;             // cell left of the face
+                    const bool act = (own || lane < TY) && (y0 + r) < ny && gxf >= -1 && gxf < nx;
+                    if (act) {
+                        C v[6][6];
 #pragma unroll
-                    for (int f = 0; f < 6; ++f)
+                        for (int f = 0; f < 6; ++f)
 #pragma unroll
-                        for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi - 1 + p + 1];
-                    C F[5];
-                    face_flux6<C>(v, 0, gamma, F, bad);
+                            for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi + p];
+                        C F[5];
+                        face_flux6<C>(v, 0, gamma, F, bad);
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) fx[f][r][fi] = F[f];
+                        for (int f = 0; f < 5; ++f) fx[f][r][fi] = F[f];
+                    }
                 }
-            }
-            // B2: y faces (y0+wv)-1/2 for wv = 0..TY, column lane
-            {
-                const int gyf = y0 + wv;                 // cell above the face
-                const bool act = (x0 + lane) < nx && gyf >= 0 && gyf <= ny;
-                if (act) {
-                    C v[6][6];
+                // B2: y faces (y0+wv)-1/2 for wv = 0..TY, column lane
+                {
+                    const int gyf = y0 + wv;                 // cell above the face
+                    const bool act = (x0 + lane) < nx && gyf >= 0 && gyf <= ny;
+                    if (act) {
+                        C v[6][6];
 #pragma unroll
-                    for (int f = 0; f < 6; ++f)
+                        for (int f = 0; f < 6; ++f)
 #pragma unroll
-                        for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
-                    C F[5];
-                    face_flux6<C>(v, 1, gamma, F, bad);
+                            for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
+                        C F[5];
+                        face_flux6<C>(v, 1, gamma, F, bad);
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) fy[f][wv][lane] = F[f];
+                        for (int f = 0; f < 5; ++f) fy[f][wv][lane] = F[f];
+                    }
                 }
             }
         }
-        // B3: z face k+1/2 from the queue (also at k = z0-1 to prime Fz_prev)
+        // B3: z face k+1/2 from the queue (also at k = z0-1 to prime Fz_prev).
+        // FP32 arithmetic: the x, y and z faces are evaluated together in one
+        // basic block every iteration (predicated stores), so their
+        // independent dependency chains interleave; every face of a direction
+        // still runs through the same instructions.
         C Fz[5];
-        if (col_out) {
+        if constexpr (sizeof(C) == 4) {
+            const int r = own ? wv : (lane < TY ? lane : 0);
+            const int fi = own ? lane + 1 : 0;
+            const int gxf = x0 + fi - 1;
+            const bool actx = body && (own || lane < TY) && (y0 + r) < ny && gxf >= -1 && gxf < nx;
+            const int gyf = y0 + wv;
+            const bool acty = body && (x0 + lane) < nx && gyf >= 0 && gyf <= ny;
+            C vx[6][6], vy[6][6], vz[6][6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    vx[f][p] = pl[f][r + G][fi + p];
+                    vy[f][p] = pl[f][wv + p][lane + G];
+                    vz[f][p] = q[f][p];
+                }
+            C Fx[5], Fy[5];
+            bool bx = false, by = false, bz = false;
+            face_flux6<C>(vx, 0, gamma, Fx, bx);
+            face_flux6<C>(vy, 1, gamma, Fy, by);
+            face_flux6<C>(vz, 2, gamma, Fz, bz);
+            if (actx) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) fx[f][r][fi] = Fx[f];
+            }
+            if (acty) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) fy[f][wv][lane] = Fy[f];
+            }
+            bad |= (actx && bx) || (acty && by) || (col_out && bz);
+        } else if (col_out) {
             C v[6][6];
 #pragma unroll
             for (int f = 0; f < 6; ++f)
