@@ -71,6 +71,7 @@ struct igr_ctx {
     void* d_Ub = nullptr;
     void* d_sig2 = nullptr;
     void* d_b = nullptr;
+    void* d_ir = nullptr;         // 1/rho written by the first sweep (FP64)
     double* d_partial = nullptr;
     double* d_scalars = nullptr;  // [0] dt, [1..5] sums, [6] residual
     int* d_flag = nullptr;
@@ -248,11 +249,12 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         C* b = static_cast<C*>(c->d_b);
         for (int it = 0; it < nsweeps; ++it) {
             IGR_TRY(launch(c, K_JACOBI, s, [&] {
+                C* ir = static_cast<C*>(c->d_ir);
                 if (it == 0)
-                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc),
+                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, ir, g, int(zc),
                                                                                       tiles_x, tiles_y);
                 else
-                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, g, int(zc),
+                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, ir, g, int(zc),
                                                                                        tiles_x, tiles_y);
             }));
             T* tmp = src;
@@ -496,7 +498,7 @@ int upload_jets(igr_ctx* c, hipStream_t s, bool sync) {
 
 void release(igr_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_owner, c->d_chi, c->d_jet, c->d_Ua, c->d_Ub, c->d_sig2, c->d_b, c->d_partial, c->d_scalars, c->d_flag};
+    void* ptrs[] = {c->d_owner, c->d_chi, c->d_jet, c->d_Ua, c->d_Ub, c->d_sig2, c->d_b, c->d_ir, c->d_partial, c->d_scalars, c->d_flag};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (double* p : c->adj)
@@ -785,6 +787,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc(&c->d_Ub, 5 * field_bytes(c, c->esize));
     if (!rc) rc = alloc(&c->d_sig2, field_bytes(c, c->esize));
     if (!rc) rc = alloc(&c->d_b, field_bytes(c, c->csize));
+    if (!rc && c->precision == IGR_F64) rc = alloc(&c->d_ir, field_bytes(c, sizeof(double)));
     if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));

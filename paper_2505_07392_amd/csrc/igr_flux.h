@@ -163,6 +163,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     };
     load_halo(z0);
 
+    C unv[5], un_next[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) unv[f] = un_next[f] = C(0);
     for (int k = z0 - 1; k < z1; ++k) {
         // shift the queue; slots hold k-2..k+3 afterwards
 #pragma unroll
@@ -172,8 +175,17 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             q[f][5] = nxt[f];
         }
         if (col_load && k + 1 < z1) load_col(k + 4, nxt);
+        // Un (read pointwise by stages 2 and 3) is fetched one plane ahead
+        if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) unv[f] = un_next[f];
+            if (col_out && k + 1 < z1) {
+                const long long o = col + (long long)(k + 1 + G) * sz;
+#pragma unroll
+                for (int f = 0; f < 5; ++f) un_next[f] = S::load(Un + f * fs + o);
+            }
+        }
         const bool body = k >= z0;
-        C unv[5];
         if (body) {
             // A: stage plane k in LDS (interior from the queue, halo from the
             // prefetched registers), then prefetch the halo of plane k+1
@@ -272,12 +284,6 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             face_flux6<C>(v, 2, gamma, Fz, bad);
         }
         if (body) {
-            // Un is read pointwise; issue its loads before the barrier
-            if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
-                const long long o = col + (long long)(k + G) * sz;
-#pragma unroll
-                for (int f = 0; f < 5; ++f) unv[f] = col_out ? S::load(Un + f * fs + o) : C(0);
-            }
             __syncthreads();
             // C: divergence and stage update
             if (col_out) {

@@ -254,10 +254,14 @@ struct SweepNb {
 template <class T, bool FIRST>
 __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
                                                  T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
-                                                 Geom g, int zc, int tiles_x, int tiles_y) {
+                                                 typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
+                                                 int tiles_x, int tiles_y) {
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
+    // FP64: the first sweep stores 1/rho (interior and the face-ghost layer)
+    // and later sweeps read it instead of dividing again (same bytes as rho)
+    constexpr bool IRS = sizeof(C) == 8;
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
     // tiles are fetched once into that XCD's L2
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
     };
     auto load_col = [&](int k, SweepCol<T, FIRST>& P) {   // for iteration k
         const long long op = zplane(k + 1);
-        P.rho = S::load(U + op);
+        P.rho = (IRS && !FIRST) ? irs[op] : S::load(U + op);
         P.sig = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
         if (FIRST) {
 #pragma unroll
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         const long long o = zplane(k);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            P.rho[n] = S::load(U + o + onb[n]);
+            P.rho[n] = (IRS && !FIRST) ? irs[o + onb[n]] : S::load(U + o + onb[n]);
             P.sig[n] = S::load(Sin + o + osg[n]);
         }
         if (FIRST) {
@@ -319,8 +323,9 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
                 for (int c = 0; c < 3; ++c) P.m[n][c] = S::load(U + (1 + c) * fs + o + onb[n]);
         }
     };
-    C ir_m = fast_rcp(S::load(U + zplane(z0 - 1)));   // rho ghost plane at the domain ends
-    C ir_c = fast_rcp(S::load(U + zplane(z0)));
+    auto inv_rho = [&](C v) { return (IRS && !FIRST) ? v : fast_rcp(v); };   // v: rho, or 1/rho stored
+    C ir_m = (IRS && !FIRST) ? irs[zplane(z0 - 1)] : fast_rcp(S::load(U + zplane(z0 - 1)));
+    C ir_c = (IRS && !FIRST) ? irs[zplane(z0)] : fast_rcp(S::load(U + zplane(z0)));
     C s_m = S::load(Sin + col + (long long)(zsig(z0 - 1) + G) * sz);
     C s_c = S::load(Sin + zplane(z0));
     C u_m[3], u_c[3];
@@ -344,11 +349,20 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
         if (k + PD < z1) load_col(k + PD, q[PD - 1]);
         if (k + 1 < z1) load_nb(k + 1, nxt);
         const long long o = zplane(k);
-        const C ir_p = fast_rcp(cc.rho);
+        const C ir_p = inv_rho(cc.rho);
         const C s_p = cc.sig;
         C irn[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(cur.rho[n]);
+        for (int n = 0; n < 4; ++n) irn[n] = inv_rho(cur.rho[n]);
+        if (IRS && FIRST) {
+            irs[o] = ir_c;
+            if (i == 0) irs[o - 1] = irn[0];
+            if (i == nx - 1) irs[o + 1] = irn[1];
+            if (j == 0) irs[o - sy] = irn[2];
+            if (j == ny - 1) irs[o + sy] = irn[3];
+            if (k == 0) irs[o - sz] = ir_m;
+            if (k == nz - 1) irs[o + sz] = ir_p;
+        }
         C bk;
         C u_p[3];
         if (FIRST) {
