@@ -232,7 +232,7 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
     T* dst = other;
     if (c->sigma_block <= 1) {
         const Geom& g = c->g;
-        const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + 3) / 4;
+        const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + SWEEP_RY - 1) / SWEEP_RY;
         const long long tiles = (long long)tiles_x * tiles_y;
 #ifndef IGR_SWEEP_BLOCKS
 #define IGR_SWEEP_BLOCKS 2048
@@ -251,11 +251,11 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             IGR_TRY(launch(c, K_JACOBI, s, [&] {
                 C* ir = static_cast<C*>(c->d_ir);
                 if (it == 0)
-                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, ir, g, int(zc),
-                                                                                      tiles_x, tiles_y);
+                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
+                                                                                             int(zc), tiles_x, tiles_y);
                 else
-                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, 4), 0, s>>>(U, src, dst, b, ir, g, int(zc),
-                                                                                       tiles_x, tiles_y);
+                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
+                                                                                              int(zc), tiles_x, tiles_y);
             }));
             T* tmp = src;
             src = dst;
@@ -310,7 +310,7 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 #define IGR_FLUX_BLOCKS_F64 2048
 #endif
 #ifndef IGR_FLUX_BLOCKS_F32
-#define IGR_FLUX_BLOCKS_F32 512
+#define IGR_FLUX_BLOCKS_F32 1024
 #endif
 template <class T>
 struct FluxShape {

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
 
 namespace igr {
 
-// One Jacobi sweep per pass, z-marching: a 64 x 4 block of columns walks a
+// One Jacobi sweep per pass, z-marching: a 64 x SWEEP_RY block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
 // lanes and rows).  Loads are issued ahead of use (see SweepCol) so that
@@ -251,8 +251,13 @@ struct SweepNb {
     C m[4][3];          // (FIRST)
 };
 
+#ifndef IGR_SWEEP_RY
+#define IGR_SWEEP_RY 4
+#endif
+constexpr int SWEEP_RY = IGR_SWEEP_RY;   // rows of a sweep block (64 x SWEEP_RY columns)
+
 template <class T, bool FIRST>
-__global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
+__global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
                                                  T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
                                                  typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
                                                  int tiles_x, int tiles_y) {
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(const T* __restrict__ U, const 
     const int by = bidx % tiles_y;
     const int bz = bidx / tiles_y;
     const int i = bx * 64 + threadIdx.x;
-    const int j = by * 4 + threadIdx.y;
+    const int j = by * SWEEP_RY + threadIdx.y;
     const int z0 = bz * zc;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     if (i >= nx || j >= ny) return;
