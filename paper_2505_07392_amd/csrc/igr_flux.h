@@ -125,41 +125,46 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         load_col(z0 + 2, nxt);
     }
 
-    // halo of the next plane, prefetched into registers (HPT values per thread)
-    constexpr int NXH = 2 * G * TY;          // x-halo cells per field
-    constexpr int NYH = 2 * G * TX;          // y-halo cells per field
-    constexpr int NH = NXH + NYH;
-    constexpr int HPT = (6 * NH + TX * (TY + 1) - 1) / (TX * (TY + 1));
-    auto halo_slot = [&](int s, int& f, int& cx, int& cy) -> bool {
-        const int h = tid + s * nthreads;
-        if (h >= 6 * NH) return false;
-        f = h / NH;
-        const int r = h - f * NH;
-        if (r < NXH) {
-            cy = r / (2 * G);
-            const int c = r - cy * 2 * G;
-            cx = c < G ? c - G : TX + (c - G);
-        } else {
-            const int r2 = r - NXH;
-            const int rr = r2 / TX;
-            cx = r2 - rr * TX;
-            cy = rr < G ? rr - G : TY + (rr - G);
-        }
-        const int gx = x0 + cx, gy = y0 + cy;
-        return gx >= -G && gx < nx + G && gy >= -G && gy < ny + G;
+    // halo of the next plane, prefetched into registers.  Regular pattern:
+    // the y-halo (2G rows x TX columns x 6 fields) goes row by row to the
+    // waves (lane = column, coalesced); the x-halo (2G columns x TY rows x
+    // 6 fields) to the first 6 * 2G * TY threads.
+    constexpr int NW = TY + 1;                   // waves per block
+    constexpr int NYR = 6 * 2 * G;               // y-halo rows over all fields
+    constexpr int HY = (NYR + NW - 1) / NW;      // y-halo rows per wave
+    constexpr int NXH = 6 * 2 * G * TY;          // x-halo cells over all fields
+    C hy[HY], hx = C(0);
+    auto y_slot = [&](int s, int& f, int& cy) -> bool {
+        const int rf = wv + s * NW;
+        if (rf >= NYR) return false;
+        f = rf / (2 * G);
+        const int rr = rf - f * 2 * G;
+        cy = rr < G ? rr - G : TY + (rr - G);
+        const int gy = y0 + cy;
+        return (x0 + lane) < nx + G && gy >= -G && gy < ny + G;
     };
-    C hv[HPT];
+    auto x_slot = [&](int& f, int& cx, int& cy) -> bool {
+        if (tid >= NXH) return false;
+        f = tid / (2 * G * TY);
+        const int r = tid - f * 2 * G * TY;
+        cy = r / (2 * G);
+        const int c = r - cy * 2 * G;
+        cx = c < G ? c - G : TX + (c - G);
+        const int gx = x0 + cx;
+        return gx >= -G && gx < nx + G && (y0 + cy) < ny + G;
+    };
+    auto fld = [&](int f) { return f < 5 ? U + f * fs : Sg; };
     auto load_halo = [&](int plane) {
         const long long zo = (long long)(plane + G) * sz;
 #pragma unroll
-        for (int s = 0; s < HPT; ++s) {
-            int f, cx, cy;
-            hv[s] = C(0);
-            if (halo_slot(s, f, cx, cy)) {
-                const long long o = zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G);
-                hv[s] = f < 5 ? S::load(U + f * fs + o) : S::load(Sg + o);
-            }
+        for (int s = 0; s < HY; ++s) {
+            int f, cy;
+            hy[s] = C(0);
+            if (y_slot(s, f, cy)) hy[s] = S::load(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
         }
+        int f, cx, cy;
+        hx = C(0);
+        if (x_slot(f, cx, cy)) hx = S::load(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G));
     };
     load_halo(z0);
 
@@ -194,9 +199,13 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                 for (int f = 0; f < 6; ++f) pl[f][wv + G][lane + G] = q[f][2];
             }
 #pragma unroll
-            for (int s = 0; s < HPT; ++s) {
+            for (int s = 0; s < HY; ++s) {
+                int f, cy;
+                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = hy[s];
+            }
+            {
                 int f, cx, cy;
-                if (halo_slot(s, f, cx, cy)) pl[f][cy + G][cx + G] = hv[s];
+                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = hx;
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
