@@ -220,7 +220,7 @@ def main():
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
+        print("bench.py measures one GPU only: this library has no multi-GPU path (the halo-exchange "
               "design is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -33,7 +33,7 @@ Method (paper section "Innovations Realized")
   reconstruction of the conserved variables and of Sigma on the stencil
   q = -2..3, conversion to primitives at the faces, inviscid flux.
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 * 7-point operator face coefficient: beta = (1/rho_c + 1/rho_nb) / 2.
 * Jacobi: exactly ``nsweeps`` sweeps, Sigma ghosts refilled from the
   previous iterate before every sweep (zero-gradient or periodic).
@@ -436,13 +436,6 @@ def run(prob: Problem, U: torch.Tensor, sigma: torch.Tensor, cfl: float,
         t += dt
         n += 1
     return U, sigma, t, n
-
-
-def plane_pressure_force(prob: Problem, U: torch.Tensor, i0: int) -> torch.Tensor:
-    """Thermodynamic pressure force on the plane between cells i0-1 and i0:
-    sum_{j,k} (p_{i0-1} + p_{i0}) / 2 * dy dz."""
-    p = pressure(prob, U)
-    return (0.5 * (p[..., i0 - 1] + p[..., i0])).sum() * (prob.dy * prob.dz)
 
 
 def to_tensor(a) -> torch.Tensor:
