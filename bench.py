@@ -27,22 +27,55 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2505_07392_amd", "csrc")
 
 
-def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int) -> float:
-    """Compulsory HBM bytes per interior cell for one launch of `kernel`."""
+def sigma_schedule(nsweeps: int, precision: str, sigma_block: int = 0):
+    """Launches of one Sigma solve as the library runs them: (first sweep,
+    two-sweep passes, later single sweeps).  The default (0) is two-sweep
+    passes in FP64 and single sweeps in the forms with FP32 arithmetic."""
+    sb = sigma_block or (2 if precision == "f64" else 1)
+    if sb > 2:
+        raise ValueError("the fused-source march passes are not modelled here")
+    if nsweeps == 0:
+        return 0, 0, 0
+    later = nsweeps - 1
+    pairs = later // 2 if sb == 2 else 0
+    return 1, pairs, later - 2 * pairs
+
+
+def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int, precision: str = "f64",
+                               sigma_block: int = 0) -> float:
+    """Compulsory HBM bytes per interior cell for one launch of `kernel`
+    (averaged over the launches of one right-hand side)."""
     if kernel == "flux_rk":
         # stage 1 reads U (5) + Sigma (1), writes 5; stages 2 and 3 also read Un (5)
         return esize * (11 + 16 + 16) / 3.0
     if kernel == "jacobi":
-        # per sweep, averaged over the first (reads rho, m, Sigma; writes
-        # Sigma, b) and the later sweeps (read Sigma, rho, b; write Sigma)
+        # first sweep: reads rho, m, Sigma; writes Sigma, b.  Later sweeps,
+        # single or two per pass: read Sigma, rho, b; write Sigma
+        nf, npair, nsingle = sigma_schedule(nsweeps, precision, sigma_block)
         first = 5 * esize + esize + csize
         later = 3 * esize + csize
-        return (first + (nsweeps - 1) * later) / nsweeps
+        return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":
         return 4 * esize + csize          # rho, m read; b written
     if kernel == "dt":
         return 5 * esize
     raise KeyError(kernel)
+
+
+def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int = 0):
+    """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
+    Sigma kernels from their measured average launch time."""
+    esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
+    csz = 8 if precision == "f64" else 4
+    out = {}
+    for k in ("flux_rk", "jacobi"):
+        ms, cnt = kt[k]
+        if cnt:
+            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, precision, sigma_block) * cells
+            gbs = ab / (ms / cnt / 1e3) / 1e9
+            out[k] = {"avg_ms": round(ms / cnt, 5), "launches": cnt, "achieved_GBs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -165,14 +198,7 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
         kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
         form = {"value": w.cells * timed_steps / el, "ms_per_step": 1e3 * el / timed_steps,
                 "device_bytes_in_use": total - free, "frac_of_288GB": (total - free) / 288e9}
-        esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[prec]
-        csz = 8 if prec == "f64" else 4
-        for k in ("flux_rk", "jacobi"):
-            ms, cnt = kt[k]
-            if cnt:
-                ab = algorithmic_bytes_per_cell(k, esz, csz, w.nsweeps) * w.cells
-                form[k] = {"avg_ms": ms / cnt, "achieved_GBs": ab / (ms / cnt / 1e3) / 1e9,
-                           "frac": ab / (ms / cnt / 1e3) / 1e9 / HBM_PEAK_GBS}
+        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps))
         if nsteps > 0:
             print(f"[bench] multi-jet {n}^3 {prec}: {nsteps}-step run", file=sys.stderr, flush=True)
             U.copy_(U0)
@@ -215,7 +241,8 @@ def main():
     ap.add_argument("--forms", default="f32,f16,bf16", help="extra precision forms timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
-    ap.add_argument("--sigma-block", type=int, default=0, help="sweeps fused per Sigma pass (0: library default)")
+    ap.add_argument("--sigma-block", type=int, default=0, choices=[0, 1, 2],
+                    help="Sigma pass structure: 1 single sweeps, 2 two-sweep passes (0: library default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -261,7 +288,8 @@ def main():
     ms, count = kt[dom]
     avg_s = ms / count / 1e3
     try:
-        abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps) * cells
+        abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps,
+                                            args.precision, args.sigma_block) * cells
     except KeyError:
         abytes = None
     workload = f"periodic_box_{args.n}"
@@ -277,9 +305,16 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x and x != args.precision]:
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, _ = run_form(w, f, args.steps, args.warmup, args.sigma_block)
-        forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps}
+        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block)
+        forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
+                    "vs_f64": None}
+        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, args.sigma_block))
 
+    if args.precision == "f64":
+        for f in forms:
+            forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
+    kernels.update({k + "_roofline": v for k, v in kernel_rooflines(kt, cells, args.precision, w.nsweeps,
+                                                                    args.sigma_block).items()})
     line = {
         "metric": "cell-updates/s per RK3 step (incl. Sigma Jacobi)",
         "value": value,
@@ -288,6 +323,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * el / args.steps,
+        "grind_ns_per_cell_step": 1e9 / value,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -113,11 +113,13 @@ typedef struct {
 
 /* Options: storage/arithmetic precision, reconstruction order (5), Jacobi
  * sweeps per right-hand side (the paper uses up to 5: "Shock treatment with
- * information geometric regularization"), and sigma_block, the number of
- * sweeps fused into one pass over memory: 1 (default, also selected by 0)
- * runs one z-marching sweep per pass with the source formed in the first;
- * 2..5 run temporally blocked passes of up to that many sweeps (fewer
- * bytes, more arithmetic per cell).  Results agree to rounding. */
+ * information geometric regularization"), and sigma_block, how the sweeps
+ * are grouped into passes over memory: 1 runs one z-marching sweep per
+ * pass (the first also forms the source); 2 runs that first pass and then
+ * two sweeps per pass (temporally blocked, reusing the stored source);
+ * 3..5 run passes of up to that many sweeps of a kernel that forms the
+ * source itself.  0 selects the default: 2 for IGR_F64, 1 for the forms
+ * with FP32 arithmetic.  Results agree to rounding. */
 typedef struct {
     int32_t precision;
     int32_t order;

@@ -57,7 +57,7 @@ struct igr_ctx {
     double dx = 0, dy = 0, dz = 0;
     int precision = IGR_F64;
     int nsweeps = 5;
-    int sigma_block = 1;   // sweeps fused per Sigma pass (1: z-marching single sweeps)
+    int sigma_block = 1;   // Sigma pass structure (1: single sweeps, 2: first + two-sweep passes, 3..5: fused march)
     int faces[6] = {0, 0, 0, 0, 0, 0};
     int device = 0;
     size_t esize = 8;     // storage bytes per element
@@ -220,17 +220,53 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
     return sigma_pass<T, 1>(c, U, Sin, Sout, s);
 }
 
+// Launch of the two-sweep pass: 64 x (PAIR_NR-2) output tiles, z chunks
+// sized for about IGR_PAIR_BLOCKS blocks of 64 x (PAIR_NR+1) threads.
+#ifndef IGR_PAIR_BLOCKS
+#define IGR_PAIR_BLOCKS 2048
+#endif
+#ifndef IGR_PAIR_ZC_MIN
+#define IGR_PAIR_ZC_MIN 8
+#endif
+template <class T>
+int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
+    using C = typename Storage<T>::C;
+    const Geom& g = c->g;
+    constexpr int NR = PAIR_NR;
+    const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + NR - 3) / (NR - 2);
+    const long long tiles = (long long)tiles_x * tiles_y;
+    long long zc = (tiles * g.n[2] + IGR_PAIR_BLOCKS - 1) / IGR_PAIR_BLOCKS;
+    if (zc < IGR_PAIR_ZC_MIN) zc = IGR_PAIR_ZC_MIN;
+    if (zc > 128) zc = 128;
+    if (zc > g.n[2]) zc = g.n[2];
+    const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
+    if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
+    const C* b = static_cast<const C*>(c->d_b);
+    const C* ir = static_cast<const C*>(c->d_ir);
+    return launch(c, K_JACOBI, s, [&] {
+        k_sweep_pair<T, NR><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(U, Sin, Sout, b, ir, g, int(zc),
+                                                                               tiles_x, tiles_y);
+    });
+}
+
 // nsweeps Jacobi sweeps from `sig` (warm start); U ghosts must be filled.
-// sigma_block == 1: one z-marching sweep per pass, the source formed in
-// the first pass and stored; otherwise passes of up to sigma_block levels
-// of the temporally blocked kernel.  The last iterate ends in `sig` (device
-// copy after an odd number of passes) and its ghosts are filled.
+// sigma_block 1: one z-marching sweep per pass, the source (and, in FP64,
+// 1/rho) formed in the first pass and stored; 2: the same first pass, then
+// two sweeps per pass; 3..5: passes of up to that many levels of the
+// temporally blocked kernel that forms the source itself.  The last
+// iterate ends in `sig` (device copy after an odd number of passes) and
+// its ghosts are filled.
 template <class T>
 int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, hipStream_t s) {
     using C = typename Storage<T>::C;
     T* src = in;
     T* dst = other;
-    if (c->sigma_block <= 1) {
+    auto swap = [&] {
+        T* tmp = src;
+        src = dst;
+        dst = tmp;
+    };
+    if (c->sigma_block <= 2) {
         const Geom& g = c->g;
         const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + SWEEP_RY - 1) / SWEEP_RY;
         const long long tiles = (long long)tiles_x * tiles_y;
@@ -247,19 +283,32 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
         if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
         C* b = static_cast<C*>(c->d_b);
-        for (int it = 0; it < nsweeps; ++it) {
-            IGR_TRY(launch(c, K_JACOBI, s, [&] {
-                C* ir = static_cast<C*>(c->d_ir);
-                if (it == 0)
+        C* ir = static_cast<C*>(c->d_ir);
+        auto single = [&](bool first) {
+            return launch(c, K_JACOBI, s, [&] {
+                if (first)
                     k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
                                                                                              int(zc), tiles_x, tiles_y);
                 else
                     k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
                                                                                               int(zc), tiles_x, tiles_y);
-            }));
-            T* tmp = src;
-            src = dst;
-            dst = tmp;
+            });
+        };
+        int left = nsweeps;
+        if (left > 0) {
+            IGR_TRY(single(true));
+            swap();
+            --left;
+        }
+        if (c->sigma_block == 2) {
+            for (; left >= 2; left -= 2) {
+                IGR_TRY(pair_pass<T>(c, U, src, dst, s));
+                swap();
+            }
+        }
+        for (; left > 0; --left) {
+            IGR_TRY(single(false));
+            swap();
         }
     } else {
         const int kmax = c->sigma_block < SigShape<T>::KMAX ? c->sigma_block : SigShape<T>::KMAX;
@@ -268,9 +317,7 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             const int k = left < kmax ? left : kmax;
             IGR_TRY(sigma_pass_k<T>(c, k, U, src, dst, s));
             left -= k;
-            T* tmp = src;
-            src = dst;
-            dst = tmp;
+            swap();
         }
     }
     *result = src;
@@ -750,7 +797,10 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->dz = grid->dz;
     c->precision = opts->precision;
     c->nsweeps = opts->nsweeps;
-    c->sigma_block = opts->sigma_block == 0 ? 1 : opts->sigma_block;
+    // default: two sweeps per pass where the arithmetic is FP64 (the
+    // sweeps are then bound by memory), single sweeps otherwise (FP32
+    // arithmetic on 2- or 4-byte storage: the single-sweep kernel is faster)
+    c->sigma_block = opts->sigma_block != 0 ? opts->sigma_block : (opts->precision == IGR_F64 ? 2 : 1);
     for (int f = 0; f < 6; ++f) c->faces[f] = bc->face[f];
     c->patches.assign(bc->patch, bc->patch + bc->npatch);
     const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;

@@ -77,6 +77,17 @@ __device__ __forceinline__ float fast_rcp(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// Block index -> logical tile index such that consecutive logical tiles run
+// on the same XCD (blocks are dealt round-robin to the 8 XCDs), so a tile's
+// y-halo rows are usually still in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int NX = 8;
+    const int full = nb - nb % NX;
+    if (b >= full) return b;
+    const int per = full / NX;
+    return (b % NX) * per + b / NX;
+}
+
 // Padded-grid geometry passed by value to every kernel.
 struct Geom {
     int n[3];          // interior extents nx, ny, nz

@@ -23,17 +23,6 @@ namespace igr {
 
 constexpr int FLUX_TX = 64;
 
-// Block index -> logical tile index such that consecutive logical tiles run
-// on the same XCD (blocks are dealt round-robin to the 8 XCDs), so a tile's
-// y-halo rows are usually still in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    constexpr int NX = 8;
-    const int full = nb - nb % NX;
-    if (b >= full) return b;
-    const int per = full / NX;
-    return (b % NX) * per + b / NX;
-}
-
 template <class C>
 __device__ __forceinline__ void face_flux6(const C (&v)[6][6], int d, C gamma, C F[5], bool& bad) {
     C UL[5], UR[5];

@@ -226,6 +226,56 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
 
 namespace igr {
 
+// One Jacobi update of the 7-point discretisation of eq. (9) at a cell,
+// in two parts: the coefficients (face coefficients beta = (1/rho_c +
+// 1/rho_nb)/2 scaled by alpha/h^2, and the reciprocal of the diagonal)
+// depend on 1/rho only and are shared by every sweep of a solve; the
+// update combines them with the source and the previous iterate.  ic =
+// 1/rho of the cell, ir = 1/rho and sg = the previous iterate at the x-,
+// x+, y-, y+, z-, z+ neighbours (sg already replaced by the cell's own
+// value where a zero-gradient face removes the neighbour).  Every sweep
+// kernel goes through these two functions, so equal inputs give equal
+// bits.
+template <class C>
+struct JacCoef {
+    C bxm, bxp, bym, byp, bzm, bzp;   // beta of the six faces
+    C rden;                           // 1 / (1/rho + alpha sum_d (beta_d- + beta_d+)/h_d^2)
+};
+
+template <class C>
+__device__ __forceinline__ JacCoef<C> jacobi_coef(C ic, const C (&ir)[6], C alpha, C hx2, C hy2, C hz2) {
+    const C half = C(0.5);
+    JacCoef<C> k;
+    k.bxm = half * (ic + ir[0]);
+    k.bxp = half * (ic + ir[1]);
+    k.bym = half * (ic + ir[2]);
+    k.byp = half * (ic + ir[3]);
+    k.bzm = half * (ic + ir[4]);
+    k.bzp = half * (ic + ir[5]);
+    C den = ic;
+    den += alpha * (k.bxp + k.bxm) * hx2;
+    den += alpha * (k.byp + k.bym) * hy2;
+    den += alpha * (k.bzp + k.bzm) * hz2;
+    k.rden = fast_rcp(den);
+    return k;
+}
+
+template <class C>
+__device__ __forceinline__ C jacobi_apply(C bk, const JacCoef<C>& k, const C (&sg)[6], C alpha, C hx2, C hy2,
+                                          C hz2) {
+    C num = bk;
+    num += alpha * (k.bxp * sg[1] + k.bxm * sg[0]) * hx2;
+    num += alpha * (k.byp * sg[3] + k.bym * sg[2]) * hy2;
+    num += alpha * (k.bzp * sg[5] + k.bzm * sg[4]) * hz2;
+    return num * k.rden;
+}
+
+template <class C>
+__device__ __forceinline__ C jacobi_point(C bk, C ic, const C (&ir)[6], const C (&sg)[6], C alpha, C hx2, C hy2,
+                                          C hz2) {
+    return jacobi_apply(bk, jacobi_coef(ic, ir, alpha, hx2, hy2, hz2), sg, alpha, hx2, hy2, hz2);
+}
+
 // One Jacobi sweep per pass, z-marching: a 64 x SWEEP_RY block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
@@ -270,13 +320,7 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
     // tiles are fetched once into that XCD's L2
-    int bidx = blockIdx.x;
-    {
-        constexpr int NXCD = 8;
-        const int nb = gridDim.x;
-        const int full = nb - nb % NXCD;
-        if (bidx < full) bidx = (bidx % NXCD) * (full / NXCD) + bidx / NXCD;
-    }
+    int bidx = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = bidx % tiles_x;
     bidx /= tiles_x;
     const int by = bidx % tiles_y;
@@ -292,7 +336,6 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
     const long long col = (long long)(j + G) * sy + (i + G);
     const C alpha = C(g.alpha);
     const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
-    const C half = C(0.5);
     // x/y neighbours: rho from the padded array, Sigma with wrap or self
     const int onb[4] = {-1, 1, -sy, sy};
     const int osg[4] = {neighbour_no_ghost(g, 0, i, -1), neighbour_no_ghost(g, 0, i, +1),
@@ -395,22 +438,9 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         } else {
             bk = cc.b;
         }
-        const C ic = ir_c;
-        const C bxm = half * (ic + irn[0]);
-        const C bxp = half * (ic + irn[1]);
-        const C bym = half * (ic + irn[2]);
-        const C byp = half * (ic + irn[3]);
-        const C bzm = half * (ic + ir_m);
-        const C bzp = half * (ic + ir_p);
-        C num = bk;
-        C den = ic;
-        num += alpha * (bxp * cur.sig[1] + bxm * cur.sig[0]) * hx2;
-        den += alpha * (bxp + bxm) * hx2;
-        num += alpha * (byp * cur.sig[3] + bym * cur.sig[2]) * hy2;
-        den += alpha * (byp + bym) * hy2;
-        num += alpha * (bzp * s_p + bzm * s_m) * hz2;
-        den += alpha * (bzp + bzm) * hz2;
-        S::store(Sout + o, num * fast_rcp(den));
+        const C irv[6] = {irn[0], irn[1], irn[2], irn[3], ir_m, ir_p};
+        const C sgv[6] = {cur.sig[0], cur.sig[1], cur.sig[2], cur.sig[3], s_m, s_p};
+        S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, alpha, hx2, hy2, hz2));
         ir_m = ir_c;
         ir_c = ir_p;
         s_m = s_c;
@@ -424,6 +454,204 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         }
         cur = nxt;
     }
+}
+
+
+// Two Jacobi sweeps per pass over memory, for the sweeps after the first
+// one of a solve (the source b and, in FP64, 1/rho were stored by the
+// first sweep).  A block of 64 x NR threads owns the columns x0..x0+63 of
+// rows y0-1..y0+NR-2 and marches through a chunk of z planes; its output
+// is the 64 x (NR-2) tile of rows y0..y0+NR-3 (level 2 needs level 1 on a
+// one-cell ring around it, level 1 needs the input on a two-cell ring).
+// One more wave holds the columns beside the tile: x0-1 and x0+64 (level 1
+// is formed there too) and x0-2 and x0+65 (input only); every row wave
+// also loads the row y0-2 (row 0) or y0+NR-1 (row NR-1) -- the other rows
+// load their own column a second time, so that every lane issues the same
+// loads.
+//
+// z-wavefront: in iteration P the input plane P (Sigma, 1/rho, b) arrives
+// and is written to LDS rings, level 1 is formed at plane P-1 and level 2
+// (the output) at plane P-2.  Every input, the z neighbours included, is
+// read back from the rings; only level 1 (and the coefficients and source
+// of the cell level 1 formed last, which level 2 reuses one plane later)
+// is kept in registers.  The rings are sized so that one barrier per plane
+// suffices: while a wave still reads planes P, P-1, P-2 another may
+// already publish plane P+1 (Sigma and 1/rho: 4 slots, b: 3, level 1: 2).
+// Loads run PD = 2 planes ahead in two register slots; the plane loop is
+// unrolled by two so that each slot is refilled by its own instructions,
+// and a slot's only consumer is the LDS write: vector-memory counters
+// complete in order, so a register copy of a pending load, or a load under
+// a branch, would make every iteration wait for all loads in flight.
+// Indices outside the grid wrap on periodic axes and clamp elsewhere;
+// cells whose value is then not the true one (beyond a zero-gradient
+// face) only feed cells beyond that face, never an output: at a
+// zero-gradient face the missing Sigma neighbour is the cell itself.
+// The intermediate level stays in the arithmetic type (it is never stored).
+#ifndef IGR_PAIR_NR
+#define IGR_PAIR_NR 7
+#endif
+constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
+
+template <class T>
+struct PairIn {     // loads of one plane for one thread
+    using C = typename Storage<T>::C;
+    C s0, ir, b;    // own column: Sigma, rho (or 1/rho when stored), b
+    C xs0, xir;     // the ring-2 row (rows 0 and NR-1; others: own column)
+};
+
+template <class T, int NR>
+__global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restrict__ U, const T* __restrict__ Sin,
+                                                            T* __restrict__ Sout,
+                                                            const typename Storage<T>::C* __restrict__ b,
+                                                            const typename Storage<T>::C* __restrict__ irs, Geom g,
+                                                            int zc, int tiles_x, int tiles_y) {
+    using S = Storage<T>;
+    using C = typename S::C;
+    constexpr bool IRS = sizeof(C) == 8;   // 1/rho stored by the first sweep (FP64)
+    constexpr int PD = 2;                   // planes loaded ahead (= register slots)
+    constexpr int W0 = 68;                  // input row: columns x0-2 .. x0+65
+    constexpr int W1 = 66;                  // level-1 and b row: x0-1 .. x0+64
+    __shared__ C ls0[4][NR + 2][W0];
+    __shared__ C lir[4][NR + 2][W0];
+    __shared__ C lb[3][NR][W1];
+    __shared__ C ls1[2][NR][W1];
+    static_assert(4 * NR - 4 <= 64, "side columns must fit one wave");
+
+    int bidx = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = bidx % tiles_x;
+    bidx /= tiles_x;
+    const int by = bidx % tiles_y;
+    const int bz = bidx / tiles_y;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = bx * 64, y0 = by * (NR - 2), z0 = bz * zc;
+    const int z1 = min(z0 + zc, nz);
+    const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+
+    // role of this thread: its column (lx, ly) in tile coordinates
+    int lx = threadIdx.x, ly = threadIdx.y;
+    bool act = true, lev1 = true, hasb = true;
+    if (threadIdx.y == NR) {
+        const int h = threadIdx.x;
+        if (h < 2 * NR) {                       // x0-1 / x0+64, every row
+            lx = h < NR ? -1 : 64;
+            ly = h % NR;
+            lev1 = ly >= 1 && ly <= NR - 2;
+        } else if (h < 4 * NR - 4) {            // x0-2 / x0+65, rows 1..NR-2
+            const int q = h - 2 * NR;
+            lx = q < NR - 2 ? -2 : 65;
+            ly = 1 + q % (NR - 2);
+            lev1 = false;
+            hasb = false;
+        } else {                                // spare lanes: load x0-2 of row 1, publish nothing
+            act = false;
+            lev1 = false;
+            hasb = false;
+            lx = -2;
+            ly = 1;
+        }
+    }
+    const int gx = x0 + lx, gy = y0 - 1 + ly;
+    const bool outp = threadIdx.y < NR && ly >= 1 && ly <= NR - 2 && gx < nx && gy < ny;
+    const bool xrow = threadIdx.y < NR && (ly == 0 || ly == NR - 1);
+    const int gyx = xrow ? (ly == 0 ? y0 - 2 : y0 + NR - 1) : gy;
+
+    auto src = [](int c, int n, int per, int lo, int hi) {
+        if (per) return ((c % n) + n) % n;
+        return c < lo ? lo : (c > hi ? hi : c);
+    };
+    const int sy = g.st[1], sz = g.st[2];
+    // Sigma and b: interior cells; 1/rho: the first ghost layer is valid too
+    const long long csig = (long long)(src(gy, ny, py, 0, ny - 1) + G) * sy + (src(gx, nx, px, 0, nx - 1) + G);
+    const long long cir = (long long)(src(gy, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
+    const long long xsig = (long long)(src(gyx, ny, py, 0, ny - 1) + G) * sy + (src(gx, nx, px, 0, nx - 1) + G);
+    const long long xir = (long long)(src(gyx, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
+    // every lane issues the same five loads at clamped planes
+    auto load = [&](int P, PairIn<T>& q) {
+        const long long os = (long long)(src(P, nz, pz, 0, nz - 1) + G) * sz;
+        const long long oi = (long long)(src(P, nz, pz, -1, nz) + G) * sz;
+        q.s0 = S::load(Sin + os + csig);
+        q.ir = IRS ? irs[oi + cir] : S::load(U + oi + cir);
+        q.b = b[os + csig];
+        q.xs0 = S::load(Sin + os + xsig);
+        q.xir = IRS ? irs[oi + xir] : S::load(U + oi + xir);
+    };
+    auto inv = [](C v) { return IRS ? v : fast_rcp(v); };
+
+    const bool xlo = !px && gx == 0, xhi = !px && gx == nx - 1;
+    const bool ylo = !py && gy == 0, yhi = !py && gy == ny - 1;
+    const C alpha = C(g.alpha);
+    const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
+    const int cx = lx + 2, cy = ly + 1;       // input-ring coordinates of the own column
+    const int xr = ly == 0 ? 0 : NR + 1;      // input-ring row of the ring-2 row
+    const int bxc = lx + 1;                   // b / level-1 column
+
+    C qs1[2] = {C(0), C(0)};                  // level 1 at planes P-3, P-2
+    // coefficients and source of the own cell at the plane level 1 formed
+    // last (level 2 updates that cell one iteration later)
+    JacCoef<C> kc = {C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+    C bprev = C(0);
+
+    auto iter = [&](int P, PairIn<T>& slot) {
+        // publish plane P, then refill the slot with plane P+PD
+        const int w4 = (P + 8) % 4, w3 = (P + 6) % 3;
+        if (act) {
+            ls0[w4][cy][cx] = slot.s0;
+            lir[w4][cy][cx] = inv(slot.ir);
+        }
+        if (hasb) lb[w3][ly][bxc] = slot.b;
+        if (xrow) {
+            ls0[w4][xr][cx] = slot.xs0;
+            lir[w4][xr][cx] = inv(slot.xir);
+        }
+        load(min(P + PD, z1 + 1), slot);
+        __syncthreads();
+        if (P < z0) return;
+        C v1 = C(0);
+        const int z = P - 1;
+        const int a4 = (P + 7) % 4;
+        // level 1 at plane P-1
+        JacCoef<C> kn = kc;
+        C bn = bprev;
+        if (lev1) {
+            const int m4 = (P + 6) % 4;
+            const C sc = ls0[a4][cy][cx];
+            const C irv[6] = {lir[a4][cy][cx - 1], lir[a4][cy][cx + 1], lir[a4][cy - 1][cx], lir[a4][cy + 1][cx],
+                              lir[m4][cy][cx], lir[w4][cy][cx]};
+            const C sgv[6] = {xlo ? sc : ls0[a4][cy][cx - 1], xhi ? sc : ls0[a4][cy][cx + 1],
+                              ylo ? sc : ls0[a4][cy - 1][cx], yhi ? sc : ls0[a4][cy + 1][cx],
+                              (!pz && z == 0) ? sc : ls0[m4][cy][cx], (!pz && z == nz - 1) ? sc : ls0[w4][cy][cx]};
+            kn = jacobi_coef(lir[a4][cy][cx], irv, alpha, hx2, hy2, hz2);
+            bn = lb[(P + 5) % 3][ly][bxc];
+            v1 = jacobi_apply(bn, kn, sgv, alpha, hx2, hy2, hz2);
+            ls1[(P + 7) & 1][ly][bxc] = v1;
+        }
+        // level 2 (output) at plane P-2, with the coefficients and source
+        // level 1 used there in the previous iteration
+        if (outp && P >= z0 + 2) {
+            const int z2 = P - 2;
+            const int a2 = (P + 6) & 1;
+            const C sc = qs1[1];
+            const C sgv[6] = {xlo ? sc : ls1[a2][ly][lx], xhi ? sc : ls1[a2][ly][lx + 2],
+                              ylo ? sc : ls1[a2][ly - 1][bxc], yhi ? sc : ls1[a2][ly + 1][bxc],
+                              (!pz && z2 == 0) ? sc : qs1[0], (!pz && z2 == nz - 1) ? sc : v1};
+            const C v2 = jacobi_apply(bprev, kc, sgv, alpha, hx2, hy2, hz2);
+            S::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
+        }
+        kc = kn;
+        bprev = bn;
+        qs1[0] = qs1[1];
+        qs1[1] = v1;
+    };
+
+    PairIn<T> pa, pb;
+    load(z0 - 2, pa);
+    load(z0 - 1, pb);
+    int P = z0 - 2;
+    for (; P + 1 <= z1 + 1; P += 2) {
+        iter(P, pa);
+        iter(P + 1, pb);
+    }
+    if (P <= z1 + 1) iter(P, pa);
 }
 
 }  // namespace igr
