@@ -357,7 +357,7 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 #define IGR_FLUX_BLOCKS_F64 2048
 #endif
 #ifndef IGR_FLUX_BLOCKS_F32
-#define IGR_FLUX_BLOCKS_F32 1024
+#define IGR_FLUX_BLOCKS_F32 2048
 #endif
 template <class T>
 struct FluxShape {

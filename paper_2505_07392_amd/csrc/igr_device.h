@@ -21,13 +21,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return uint16_t(u >> 16);
 }
 
-// Storage type T -> arithmetic type C with load/store conversions.
+// Storage type T -> arithmetic type C with load/store conversions.  R is
+// the register form of a loaded value before conversion: kernels that load
+// ahead keep R in their prefetch registers and convert where the value is
+// used, so that the conversion does not wait for the load to arrive.
 template <class T>
 struct Storage;
 
 template <>
 struct Storage<double> {
     using C = double;
+    using R = double;
+    __device__ __forceinline__ static R load_raw(const double* p) { return *p; }
+    __device__ __forceinline__ static C cvt(R r) { return r; }
     __device__ __forceinline__ static double load(const double* p) { return *p; }
     __device__ __forceinline__ static void store(double* p, double v) { *p = v; }
 };
@@ -35,6 +41,9 @@ struct Storage<double> {
 template <>
 struct Storage<float> {
     using C = float;
+    using R = float;
+    __device__ __forceinline__ static R load_raw(const float* p) { return *p; }
+    __device__ __forceinline__ static C cvt(R r) { return r; }
     __device__ __forceinline__ static float load(const float* p) { return *p; }
     __device__ __forceinline__ static void store(float* p, float v) { *p = v; }
 };
@@ -42,9 +51,10 @@ struct Storage<float> {
 template <>
 struct Storage<bf16> {
     using C = float;
-    __device__ __forceinline__ static float load(const bf16* p) {
-        return __uint_as_float(uint32_t(p->bits) << 16);
-    }
+    using R = uint32_t;   // the 16 stored bits
+    __device__ __forceinline__ static R load_raw(const bf16* p) { return p->bits; }
+    __device__ __forceinline__ static C cvt(R r) { return __uint_as_float(r << 16); }
+    __device__ __forceinline__ static float load(const bf16* p) { return cvt(load_raw(p)); }
     __device__ __forceinline__ static void store(bf16* p, float v) { p->bits = f32_to_bf16_rne(v); }
 };
 
@@ -55,6 +65,11 @@ using f16 = _Float16;
 template <>
 struct Storage<f16> {
     using C = float;
+    using R = uint32_t;   // the 16 stored bits
+    __device__ __forceinline__ static R load_raw(const f16* p) {
+        return __builtin_bit_cast(uint16_t, *p);
+    }
+    __device__ __forceinline__ static C cvt(R r) { return float(__builtin_bit_cast(f16, uint16_t(r))); }
     __device__ __forceinline__ static float load(const f16* p) { return float(*p); }
     __device__ __forceinline__ static void store(f16* p, float v) { *p = f16(v); }
 };

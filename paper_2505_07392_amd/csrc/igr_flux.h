@@ -89,27 +89,30 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
     for (int f = 0; f < 5; ++f) Fz_prev[f] = C(0);
 
-    auto load_col = [&](int plane, C (&v)[6]) {
+    // prefetched values stay in the storage's register form R until used
+    // (a 16-bit value converted at its load would wait for that load)
+    using R = typename S::R;
+    auto load_col = [&](int plane, R (&v)[6]) {
         const long long o = col + (long long)(plane + G) * sz;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) v[f] = S::load(U + f * fs + o);
-        v[5] = S::load(Sg + o);
+        for (int f = 0; f < 5; ++f) v[f] = S::load_raw(U + f * fs + o);
+        v[5] = S::load_raw(Sg + o);
     };
     // prime with planes z0-3 .. z0+1 (slot p holds plane z0-3+p) and keep
     // plane z0+2 in `nxt`; every iteration shifts, moves `nxt` into slot 5
     // and issues the load of the plane after it, so each column load has a
     // whole iteration to arrive.  The loop starts at k = z0 - 1 to compute
     // face z0 - 1/2 with the same code as every other z face.
-    C nxt[6];
+    R nxt[6];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) nxt[f] = f == 0 ? C(1) : (f == 4 ? C(2.5) : C(0));
+    for (int f = 0; f < 6; ++f) nxt[f] = R(0);
     if (col_load) {
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
-            C v[6];
+            R v[6];
             load_col(z0 - 3 + p, v);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) q[f][p + 1] = v[f];
+            for (int f = 0; f < 6; ++f) q[f][p + 1] = S::cvt(v[f]);
         }
         load_col(z0 + 2, nxt);
     }
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     constexpr int NYR = 6 * 2 * G;               // y-halo rows over all fields
     constexpr int HY = (NYR + NW - 1) / NW;      // y-halo rows per wave
     constexpr int NXH = 6 * 2 * G * TY;          // x-halo cells over all fields
-    C hy[HY], hx = C(0);
+    R hy[HY], hx = R(0);
     auto y_slot = [&](int s, int& f, int& cy) -> bool {
         const int rf = wv + s * NW;
         if (rf >= NYR) return false;
@@ -148,35 +151,39 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
         for (int s = 0; s < HY; ++s) {
             int f, cy;
-            hy[s] = C(0);
-            if (y_slot(s, f, cy)) hy[s] = S::load(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
+            hy[s] = R(0);
+            if (y_slot(s, f, cy)) hy[s] = S::load_raw(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
         }
         int f, cx, cy;
-        hx = C(0);
-        if (x_slot(f, cx, cy)) hx = S::load(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G));
+        hx = R(0);
+        if (x_slot(f, cx, cy)) hx = S::load_raw(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G));
     };
     load_halo(z0);
 
-    C unv[5], un_next[5];
+    C unv[5];
+    R un_next[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) unv[f] = un_next[f] = C(0);
+    for (int f = 0; f < 5; ++f) {
+        unv[f] = C(0);
+        un_next[f] = R(0);
+    }
     for (int k = z0 - 1; k < z1; ++k) {
         // shift the queue; slots hold k-2..k+3 afterwards
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
 #pragma unroll
             for (int p = 0; p < 5; ++p) q[f][p] = q[f][p + 1];
-            q[f][5] = nxt[f];
+            if (col_load) q[f][5] = S::cvt(nxt[f]);
         }
         if (col_load && k + 1 < z1) load_col(k + 4, nxt);
         // Un (read pointwise by stages 2 and 3) is fetched one plane ahead
         if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) unv[f] = un_next[f];
+            for (int f = 0; f < 5; ++f) unv[f] = S::cvt(un_next[f]);
             if (col_out && k + 1 < z1) {
                 const long long o = col + (long long)(k + 1 + G) * sz;
 #pragma unroll
-                for (int f = 0; f < 5; ++f) un_next[f] = S::load(Un + f * fs + o);
+                for (int f = 0; f < 5; ++f) un_next[f] = S::load_raw(Un + f * fs + o);
             }
         }
         const bool body = k >= z0;
@@ -190,11 +197,11 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
             for (int s = 0; s < HY; ++s) {
                 int f, cy;
-                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = hy[s];
+                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = S::cvt(hy[s]);
             }
             {
                 int f, cx, cy;
-                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = hx;
+                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = S::cvt(hx);
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();

@@ -288,17 +288,22 @@ __device__ __forceinline__ C jacobi_point(C bk, C ic, const C (&ir)[6], const C 
 // of plane k+1 (which miss to HBM) are fetched PD iterations ahead; the x/y
 // neighbours of plane k (mostly L1/L2 hits: other threads' columns) one
 // iteration ahead.
+// Values are kept in the storage's register form R (converted where used)
+// so that a conversion does not wait for its load.  In FP64 later sweeps
+// `rho` holds the stored 1/rho.
 template <class T, bool FIRST>
 struct SweepCol {
     using C = typename Storage<T>::C;
-    C rho, sig, b;      // rho, Sigma_in at plane k+1; b at plane k (later sweeps)
-    C m[3];             // m at plane k+1 (FIRST)
+    using R = typename Storage<T>::R;
+    R rho, sig;         // rho, Sigma_in at plane k+1
+    C b;                // b at plane k (later sweeps)
+    R m[3];             // m at plane k+1 (FIRST)
 };
 template <class T, bool FIRST>
 struct SweepNb {
-    using C = typename Storage<T>::C;
-    C rho[4], sig[4];   // x/y neighbours of plane k
-    C m[4][3];          // (FIRST)
+    using R = typename Storage<T>::R;
+    R rho[4], sig[4];   // x/y neighbours of plane k
+    R m[4][3];          // (FIRST)
 };
 
 #ifndef IGR_SWEEP_RY
@@ -348,11 +353,14 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
     };
     auto load_col = [&](int k, SweepCol<T, FIRST>& P) {   // for iteration k
         const long long op = zplane(k + 1);
-        P.rho = (IRS && !FIRST) ? irs[op] : S::load(U + op);
-        P.sig = S::load(Sin + col + (long long)(zsig(k + 1) + G) * sz);
+        if constexpr (IRS && !FIRST)
+            P.rho = irs[op];
+        else
+            P.rho = S::load_raw(U + op);
+        P.sig = S::load_raw(Sin + col + (long long)(zsig(k + 1) + G) * sz);
         if (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) P.m[c] = S::load(U + (1 + c) * fs + op);
+            for (int c = 0; c < 3; ++c) P.m[c] = S::load_raw(U + (1 + c) * fs + op);
         } else {
             P.b = b[zplane(k)];
         }
@@ -361,17 +369,27 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         const long long o = zplane(k);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            P.rho[n] = (IRS && !FIRST) ? irs[o + onb[n]] : S::load(U + o + onb[n]);
-            P.sig[n] = S::load(Sin + o + osg[n]);
+            if constexpr (IRS && !FIRST)
+                P.rho[n] = irs[o + onb[n]];
+            else
+                P.rho[n] = S::load_raw(U + o + onb[n]);
+            P.sig[n] = S::load_raw(Sin + o + osg[n]);
         }
         if (FIRST) {
 #pragma unroll
             for (int n = 0; n < 4; ++n)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) P.m[n][c] = S::load(U + (1 + c) * fs + o + onb[n]);
+                for (int c = 0; c < 3; ++c) P.m[n][c] = S::load_raw(U + (1 + c) * fs + o + onb[n]);
         }
     };
-    auto inv_rho = [&](C v) { return (IRS && !FIRST) ? v : fast_rcp(v); };   // v: rho, or 1/rho stored
+    using R = typename S::R;
+    // v: rho (register form), or 1/rho stored (FP64 later sweeps)
+    auto inv_rho = [&](R v) {
+        if constexpr (IRS && !FIRST)
+            return v;
+        else
+            return fast_rcp(S::cvt(v));
+    };
     C ir_m = (IRS && !FIRST) ? irs[zplane(z0 - 1)] : fast_rcp(S::load(U + zplane(z0 - 1)));
     C ir_c = (IRS && !FIRST) ? irs[zplane(z0)] : fast_rcp(S::load(U + zplane(z0)));
     C s_m = S::load(Sin + col + (long long)(zsig(z0 - 1) + G) * sz);
@@ -398,7 +416,7 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         if (k + 1 < z1) load_nb(k + 1, nxt);
         const long long o = zplane(k);
         const C ir_p = inv_rho(cc.rho);
-        const C s_p = cc.sig;
+        const C s_p = S::cvt(cc.sig);
         C irn[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) irn[n] = inv_rho(cur.rho[n]);
@@ -415,14 +433,14 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         C u_p[3];
         if (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) u_p[c] = cc.m[c] * ir_p;
+            for (int c = 0; c < 3; ++c) u_p[c] = S::cvt(cc.m[c]) * ir_p;
             C Gm[3][3];
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const C sc = C(0.5) * C(g.ih[d]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    Gm[c][d] = (cur.m[2 * d + 1][c] * irn[2 * d + 1] - cur.m[2 * d][c] * irn[2 * d]) * sc;
+                    Gm[c][d] = (S::cvt(cur.m[2 * d + 1][c]) * irn[2 * d + 1] - S::cvt(cur.m[2 * d][c]) * irn[2 * d]) * sc;
             }
             const C scz = C(0.5) * C(g.ih[2]);
 #pragma unroll
@@ -439,7 +457,7 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
             bk = cc.b;
         }
         const C irv[6] = {irn[0], irn[1], irn[2], irn[3], ir_m, ir_p};
-        const C sgv[6] = {cur.sig[0], cur.sig[1], cur.sig[2], cur.sig[3], s_m, s_p};
+        const C sgv[6] = {S::cvt(cur.sig[0]), S::cvt(cur.sig[1]), S::cvt(cur.sig[2]), S::cvt(cur.sig[3]), s_m, s_p};
         S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, alpha, hx2, hy2, hz2));
         ir_m = ir_c;
         ir_c = ir_p;
@@ -493,10 +511,12 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
 constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
 
 template <class T>
-struct PairIn {     // loads of one plane for one thread
+struct PairIn {     // loads of one plane for one thread (register form R)
     using C = typename Storage<T>::C;
-    C s0, ir, b;    // own column: Sigma, rho (or 1/rho when stored), b
-    C xs0, xir;     // the ring-2 row (rows 0 and NR-1; others: own column)
+    using R = typename Storage<T>::R;
+    R s0, ir;       // own column: Sigma, rho (or 1/rho when stored)
+    C b;            // own column: b
+    R xs0, xir;     // the ring-2 row (rows 0 and NR-1; others: own column)
 };
 
 template <class T, int NR>
@@ -569,13 +589,24 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     auto load = [&](int P, PairIn<T>& q) {
         const long long os = (long long)(src(P, nz, pz, 0, nz - 1) + G) * sz;
         const long long oi = (long long)(src(P, nz, pz, -1, nz) + G) * sz;
-        q.s0 = S::load(Sin + os + csig);
-        q.ir = IRS ? irs[oi + cir] : S::load(U + oi + cir);
+        q.s0 = S::load_raw(Sin + os + csig);
         q.b = b[os + csig];
-        q.xs0 = S::load(Sin + os + xsig);
-        q.xir = IRS ? irs[oi + xir] : S::load(U + oi + xir);
+        q.xs0 = S::load_raw(Sin + os + xsig);
+        if constexpr (IRS) {
+            q.ir = irs[oi + cir];
+            q.xir = irs[oi + xir];
+        } else {
+            q.ir = S::load_raw(U + oi + cir);
+            q.xir = S::load_raw(U + oi + xir);
+        }
     };
-    auto inv = [](C v) { return IRS ? v : fast_rcp(v); };
+    using R = typename S::R;
+    auto inv = [](R v) {
+        if constexpr (IRS)
+            return v;
+        else
+            return fast_rcp(S::cvt(v));
+    };
 
     const bool xlo = !px && gx == 0, xhi = !px && gx == nx - 1;
     const bool ylo = !py && gy == 0, yhi = !py && gy == ny - 1;
@@ -595,12 +626,12 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
         // publish plane P, then refill the slot with plane P+PD
         const int w4 = (P + 8) % 4, w3 = (P + 6) % 3;
         if (act) {
-            ls0[w4][cy][cx] = slot.s0;
+            ls0[w4][cy][cx] = S::cvt(slot.s0);
             lir[w4][cy][cx] = inv(slot.ir);
         }
         if (hasb) lb[w3][ly][bxc] = slot.b;
         if (xrow) {
-            ls0[w4][xr][cx] = slot.xs0;
+            ls0[w4][xr][cx] = S::cvt(slot.xs0);
             lir[w4][xr][cx] = inv(slot.xir);
         }
         load(min(P + PD, z1 + 1), slot);
