@@ -171,3 +171,27 @@ def test_residual_decreases_with_sweeps():
         sk, _ = ref.sigma_solve(prob, U, s, nsweeps=k)
         r.append(ref.sigma_residual_l2(prob, U, sk))
     assert r[0] > r[1] > r[2]
+
+
+def test_residual_is_the_norm_of_the_assembled_system():
+    """sigma_residual_l2 = ||b - A Sigma||_2 with A from the brute-force
+    assembly: with zero momentum in the domain the source is non-zero only
+    in the cells beside the jet disc (whose ghost state moves), so the
+    residual of a random Sigma is ||b - A Sigma|| with that sparse b; with
+    momentum, the residual at the dense solution of A Sigma = b is zero to
+    round-off."""
+    prob = _problem()
+    rho, U, b, sig = _fields(prob, 6)
+    D, O = _assemble(prob, rho)
+    A = np.diag(D) - O
+    U0 = U.clone()
+    U0[1:4] = 0.0
+    b0 = ref.sigma_source(prob, ref.pad_state(prob, U0)).numpy()
+    assert np.count_nonzero(b0[:, :, 1:]) == 0      # only the x = 0 layer sees the moving jet ghost
+    got = ref.sigma_residual_l2(prob, U0, torch.from_numpy(sig))
+    want = np.linalg.norm(b0.ravel() - A @ sig.ravel())
+    assert abs(got - want) <= 1e-13 * want
+    bsrc = ref.sigma_source(prob, ref.pad_state(prob, U)).numpy().ravel()
+    assert np.abs(bsrc).max() > 0
+    exact = np.linalg.solve(A, bsrc).reshape(prob.shape)
+    assert ref.sigma_residual_l2(prob, U, torch.from_numpy(exact)) <= 1e-12 * np.linalg.norm(bsrc)
