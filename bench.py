@@ -124,12 +124,12 @@ def cpu_baseline(w, seconds_target: float = 15.0):
                       f"seed as the 256^3 workload), {el:.1f} s"}
 
 
-def run_form(w, precision, steps, warmup, sigma_block=0):
+def run_form(w, precision, steps, warmup, sigma_block=0, order=5):
     import torch
 
     from paper_2505_07392_amd import igr
 
-    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block)
+    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block, order=order)
     U = s.state_from(w.U)
     sig = s.new_field()
     for _ in range(warmup):
@@ -243,6 +243,7 @@ def main():
     ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
     ap.add_argument("--sigma-block", type=int, default=0, choices=[0, 1, 2],
                     help="Sigma pass structure: 1 single sweeps, 2 two-sweep passes (0: library default)")
+    ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -281,7 +282,7 @@ def main():
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
     csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 
-    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block)
+    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order)
     value = cells * args.steps / el
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -294,7 +295,7 @@ def main():
         abytes = None
     workload = f"periodic_box_{args.n}"
     achieved = abytes / avg_s / 1e9 if abytes else None
-    traffic = load_traffic(dom, f"{workload}_{args.precision}")
+    traffic = load_traffic(dom, f"{workload}_{args.precision}") if args.order == 5 and not args.sigma_block else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                 "avg_launch_ms": ms / count, "launches": count,
@@ -305,7 +306,7 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x and x != args.precision]:
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block)
+        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order)
         forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
                     "vs_f64": None}
         forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, args.sigma_block))
@@ -331,7 +332,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{workload} periodic box {args.n}^3, rms Mach 1.5, alpha=dx^2, "
                                f"{w.nsweeps} Jacobi sweeps, CFL 0.5", "cells": cells,
-                   "sweeps": w.nsweeps, "precision": args.precision},
+                   "sweeps": w.nsweeps, "precision": args.precision, "order": args.order},
         "roofline": roofline,
         "kernels": kernels,
         "forms": forms,

@@ -111,7 +111,9 @@ typedef struct {
     const igr_patch *patch;
 } igr_bc;
 
-/* Options: storage/arithmetic precision, reconstruction order (5), Jacobi
+/* Options: storage/arithmetic precision, reconstruction order (5, or 3:
+ * the paper's third- or fifth-order finite volume method, "Discretization";
+ * the adjoint entry points need 5), Jacobi
  * sweeps per right-hand side (the paper uses up to 5: "Shock treatment with
  * information geometric regularization"), and sigma_block, how the sweeps
  * are grouped into passes over memory: 1 runs one z-marching sweep per
@@ -175,7 +177,8 @@ int igr_rhs(igr_ctx *ctx, void *U, void *sigma, void *rhs, void *stream);
 int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, double *dt_used,
              void *stream);
 
-/* Discrete adjoint of igr_rhs (FP64 contexts; vector-Jacobian product of
+/* Discrete adjoint of igr_rhs (FP64 contexts with fifth-order
+ * reconstruction, else IGR_EUNSUPPORTED; vector-Jacobian product of
  * the map (U, sigma_prev) -> (L(U), sigma_new) and of the jet-disc
  * states).  Given rhs_bar (5 fields) and sigma_bar (cotangent of the new
  * Sigma), writes U_bar (5 fields) and sigma_prev_bar; only interiors are
@@ -188,7 +191,8 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
 int igr_rhs_adjoint(igr_ctx *ctx, void *U, const void *sigma_prev, const void *rhs_bar, const void *sigma_bar,
                     void *U_bar, void *sigma_prev_bar, double *patch_bar, void *stream);
 
-/* Discrete adjoint of one igr_step with a fixed time step dt > 0 (FP64):
+/* Discrete adjoint of one igr_step with a fixed time step dt > 0 (FP64,
+ * fifth-order reconstruction):
  * given the step's input (U_n, sigma_n) and the cotangents of its output
  * (U_bar_np1, sigma_bar_np1), writes the cotangents of its input (U_bar_n,
  * sigma_bar_n) and, if patch_bar is not NULL, of the primitive jet states

@@ -27,8 +27,9 @@ Method (paper section "Innovations Realized")
 * "Discretization" subsection: second-order central velocity gradients for
   the left side of eq. (9), a 7-point stencil for the operator on the right,
   a fixed number of Jacobi sweeps warm-started from the previous Sigma,
-  fifth-order linear reconstruction, Lax-Friedrichs interface fluxes and a
-  third-order SSP Runge-Kutta stepper (Gottlieb & Shu 1998).
+  fifth-order (or third-order) linear reconstruction, Lax-Friedrichs
+  interface fluxes and a third-order SSP Runge-Kutta stepper (Gottlieb &
+  Shu 1998).
 * "The algorithm" subsection, Algorithm 1: dimension-by-dimension faces,
   reconstruction of the conserved variables and of Sigma on the stencil
   q = -2..3, conversion to primitives at the faces, inviscid flux.
@@ -48,14 +49,15 @@ Readings where the paper is silent:
 * dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d.
 
 Parity pins (tests/test_oracle_*.py): reconstruction polynomial exactness
+(degree <= 4 for the fifth-order, <= 2 for the third-order interpolant)
 and mirror symmetry; source exactness for linear velocity fields; Jacobi
 sweep against a brute-force dense assembly, symmetry of the assembled
 operator, convergence to a dense solve, the 6/7 contraction factor;
 flux consistency F(U, U) = F(U); uniform-state preservation; axis
 permutation and mirror symmetry; alpha = 0 against an independently written
 per-cell Lax-Friedrichs code; Sod against the exact Riemann solution;
-periodic conservation; fifth-order convergence on an entropy wave; RK3
-against its stability polynomial.
+periodic conservation; fifth- and third-order convergence on an entropy
+wave; RK3 against its stability polynomial.
 """
 
 from __future__ import annotations
@@ -76,6 +78,13 @@ EXTRAP = "extrap"
 RECON_LEFT = (2.0, -13.0, 47.0, 27.0, -3.0)
 RECON_RIGHT = (-3.0, 27.0, 47.0, -13.0, 2.0)
 RECON_DENOM = 60.0
+
+# Third-order linear reconstruction from three cell averages (the paper's
+# other order, "Discretization"; the optimal linear weights of WENO3).  Left
+# state at face i+1/2 from cells i-1..i+1, right state from cells i..i+2.
+RECON3_LEFT = (-1.0, 5.0, 2.0)
+RECON3_RIGHT = (2.0, 5.0, -1.0)
+RECON3_DENOM = 6.0
 
 
 class NonPhysicalState(RuntimeError):
@@ -117,6 +126,7 @@ class Problem:
     faces: Sequence[str] = (EXTRAP,) * 6  # -x, +x, -y, +y, -z, +z
     patches: Sequence[Patch] = field(default_factory=tuple)
     nsweeps: int = 5
+    order: int = 5          # reconstruction order: 5 or 3 ("Discretization")
 
     @property
     def shape(self):
@@ -317,9 +327,15 @@ def reconstruct(prob: Problem, qpad: torch.Tensor, d: int, g: int = G):
                 t = t.narrow(-1 - ax, g, prob.n(ax))
         return t
 
-    # face f = i + 1/2 with i = f - 1: left uses cells i-2..i+2, right i-1..i+3
-    left = sum(c * take(o) for c, o in zip(RECON_LEFT, (-3, -2, -1, 0, 1))) / RECON_DENOM
-    right = sum(c * take(o) for c, o in zip(RECON_RIGHT, (-2, -1, 0, 1, 2))) / RECON_DENOM
+    # face f = i + 1/2 with i = f - 1 (take(o) is cell i + 1 + o)
+    if prob.order == 5:       # left: cells i-2..i+2, right: i-1..i+3
+        left = sum(c * take(o) for c, o in zip(RECON_LEFT, (-3, -2, -1, 0, 1))) / RECON_DENOM
+        right = sum(c * take(o) for c, o in zip(RECON_RIGHT, (-2, -1, 0, 1, 2))) / RECON_DENOM
+    elif prob.order == 3:     # left: cells i-1..i+1, right: i..i+2
+        left = sum(c * take(o) for c, o in zip(RECON3_LEFT, (-2, -1, 0))) / RECON3_DENOM
+        right = sum(c * take(o) for c, o in zip(RECON3_RIGHT, (-1, 0, 1))) / RECON3_DENOM
+    else:
+        raise ValueError("reconstruction order must be 3 or 5")
     return left, right
 
 

@@ -57,6 +57,7 @@ struct igr_ctx {
     double dx = 0, dy = 0, dz = 0;
     int precision = IGR_F64;
     int nsweeps = 5;
+    int order = 5;         // reconstruction order (5 or 3)
     int sigma_block = 1;   // Sigma pass structure (1: single sweeps, 2: first + two-sweep passes, 3..5: fused march)
     int faces[6] = {0, 0, 0, 0, 0, 0};
     int device = 0;
@@ -397,8 +398,12 @@ int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const d
     const FluxLaunch L = flux_launch(c->g, TY, FluxShape<T>::BLOCKS);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
-        k_flux_tiled<T, MODE, TY><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-            U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
+        if (c->order == 3)
+            k_flux_tiled<T, MODE, TY, 3><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
+        else
+            k_flux_tiled<T, MODE, TY, 5><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
     });
 }
 
@@ -783,7 +788,8 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (opts->precision != IGR_F64 && opts->precision != IGR_F32 && opts->precision != IGR_BF16_F32 &&
         opts->precision != IGR_F16_F32)
         return fail(IGR_EINVAL, "unknown precision");
-    if (opts->order != 5) return fail(IGR_EUNSUPPORTED, "only fifth-order reconstruction is implemented");
+    if (opts->order != 5 && opts->order != 3)
+        return fail(IGR_EUNSUPPORTED, "reconstruction order must be 5 or 3");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
     if (opts->sigma_block < 0 || opts->sigma_block > 5) return fail(IGR_EINVAL, "sigma_block must be in 0..5");
 
@@ -797,6 +803,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->dz = grid->dz;
     c->precision = opts->precision;
     c->nsweeps = opts->nsweeps;
+    c->order = opts->order;
     // default: two sweeps per pass where the arithmetic is FP64 (the
     // sweeps are then bound by memory), single sweeps otherwise (FP32
     // arithmetic on 2- or 4-byte storage: the single-sweep kernel is faster)
@@ -972,6 +979,7 @@ int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* r
     if (!ctx || !U || !sigma_prev || !rhs_bar || !sigma_bar || !U_bar || !sigma_prev_bar)
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
+    if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
     // inputs may alias outputs: stage them
@@ -996,6 +1004,7 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     if (!ctx || !U_n || !sigma_n || !U_bar_np1 || !sigma_bar_np1 || !U_bar_n || !sigma_bar_n)
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
+    if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));

@@ -23,20 +23,32 @@ namespace igr {
 
 constexpr int FLUX_TX = 64;
 
-template <class C>
+// LLF flux at the face between cells 2 and 3 of v[field][0..5] (cells
+// i-2..i+3 around face i+1/2) with ORDER-th order reconstruction (5 or 3;
+// the third-order stencils use cells i-1..i+2 only).
+template <class C, int ORDER>
 __device__ __forceinline__ void face_flux6(const C (&v)[6][6], int d, C gamma, C F[5], bool& bad) {
+    C Q[6][2];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if constexpr (ORDER == 5) {
+            Q[f][0] = recon_left(v[f][0], v[f][1], v[f][2], v[f][3], v[f][4]);
+            Q[f][1] = recon_right(v[f][1], v[f][2], v[f][3], v[f][4], v[f][5]);
+        } else {
+            Q[f][0] = recon3_left(v[f][1], v[f][2], v[f][3]);
+            Q[f][1] = recon3_right(v[f][2], v[f][3], v[f][4]);
+        }
+    }
     C UL[5], UR[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-        UL[f] = recon_left(v[f][0], v[f][1], v[f][2], v[f][3], v[f][4]);
-        UR[f] = recon_right(v[f][1], v[f][2], v[f][3], v[f][4], v[f][5]);
+        UL[f] = Q[f][0];
+        UR[f] = Q[f][1];
     }
-    const C SL = recon_left(v[5][0], v[5][1], v[5][2], v[5][3], v[5][4]);
-    const C SR = recon_right(v[5][1], v[5][2], v[5][3], v[5][4], v[5][5]);
-    llf_flux<C>(UL, UR, SL, SR, d, gamma, F, bad);
+    llf_flux<C>(UL, UR, Q[5][0], Q[5][1], d, gamma, F, bad);
 }
 
-template <class T, int MODE, int TY>
+template <class T, int MODE, int TY, int ORDER>
 __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out, const double* __restrict__ dtp,
     double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc) {
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                             for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi + p];
                         C F[5];
-                        face_flux6<C>(v, 0, gamma, F, bad);
+                        face_flux6<C, ORDER>(v, 0, gamma, F, bad);
 #pragma unroll
                         for (int f = 0; f < 5; ++f) fx[f][r][fi] = F[f];
                     }
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                             for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
                         C F[5];
-                        face_flux6<C>(v, 1, gamma, F, bad);
+                        face_flux6<C, ORDER>(v, 1, gamma, F, bad);
 #pragma unroll
                         for (int f = 0; f < 5; ++f) fy[f][wv][lane] = F[f];
                     }
@@ -268,9 +280,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                 }
             C Fx[5], Fy[5];
             bool bx = false, by = false, bz = false;
-            face_flux6<C>(vx, 0, gamma, Fx, bx);
-            face_flux6<C>(vy, 1, gamma, Fy, by);
-            face_flux6<C>(vz, 2, gamma, Fz, bz);
+            face_flux6<C, ORDER>(vx, 0, gamma, Fx, bx);
+            face_flux6<C, ORDER>(vy, 1, gamma, Fy, by);
+            face_flux6<C, ORDER>(vz, 2, gamma, Fz, bz);
             if (actx) {
 #pragma unroll
                 for (int f = 0; f < 5; ++f) fx[f][r][fi] = Fx[f];
@@ -286,7 +298,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             for (int f = 0; f < 6; ++f)
 #pragma unroll
                 for (int p = 0; p < 6; ++p) v[f][p] = q[f][p];
-            face_flux6<C>(v, 2, gamma, Fz, bad);
+            face_flux6<C, ORDER>(v, 2, gamma, Fz, bad);
         }
         if (body) {
             __syncthreads();

@@ -168,6 +168,18 @@ __device__ __forceinline__ C recon_right(C b, C c, C d, C e, C f) {
     return (C(-3) * b + C(27) * c + C(47) * d - C(13) * e + C(2) * f) * (C(1) / C(60));
 }
 
+// Third-order linear reconstruction (the paper's other order,
+// "Discretization"; the optimal linear weights of WENO3): left state at
+// face i+1/2 from cells i-1..i+1, right state from cells i..i+2.
+template <class C>
+__device__ __forceinline__ C recon3_left(C b, C c, C d) {
+    return (C(-1) * b + C(5) * c + C(2) * d) * (C(1) / C(6));
+}
+template <class C>
+__device__ __forceinline__ C recon3_right(C c, C d, C e) {
+    return (C(2) * c + C(5) * d - C(1) * e) * (C(1) / C(6));
+}
+
 // Square root of a sound speed: correctly rounded in FP64, the hardware
 // instruction (1 ulp) in FP32.
 __device__ __forceinline__ double face_sqrt(double x) { return sqrt(x); }

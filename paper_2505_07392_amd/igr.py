@@ -121,7 +121,7 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, *, gamma: float = 1.4,
                  alpha: float = 0.0, faces: Sequence[str] = ("extrap",) * 6, jets: Iterable = (),
-                 nsweeps: int = 5, precision: str = "f64", sigma_block: int = 0, device=None):
+                 nsweeps: int = 5, precision: str = "f64", sigma_block: int = 0, order: int = 5, device=None):
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {list(PRECISION)}")
         self.nx, self.ny, self.nz = nx, ny, nz
@@ -138,7 +138,8 @@ class Solver:
         for i, j in enumerate(jets):
             self._patches[i] = Patch(j.yc, j.zc, j.r, getattr(j, "width", 0.0), j.rho, j.ux, j.uy, j.uz, j.p)
         bc = BC((ctypes.c_int32 * 6)(*[BC_KIND[f] for f in faces]), len(jets), self._patches)
-        opts = Opts(PRECISION[precision][0], 5, nsweeps, sigma_block)
+        self.order = order
+        opts = Opts(PRECISION[precision][0], order, nsweeps, sigma_block)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().igr_init(ctypes.byref(Grid(nx, ny, nz, dx, dy, dz)), gamma, alpha, ctypes.byref(bc),
@@ -147,10 +148,10 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, precision: str = "f64", nsweeps: Optional[int] = None, sigma_block: int = 0,
-                      device=None) -> "Solver":
+                      order: int = 5, device=None) -> "Solver":
         return cls(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha, faces=tuple(w.faces),
                    jets=w.jets, nsweeps=w.nsweeps if nsweeps is None else nsweeps, precision=precision,
-                   sigma_block=sigma_block, device=device)
+                   sigma_block=sigma_block, order=order, device=device)
 
     # -- memory ------------------------------------------------------------
     def new_state(self) -> torch.Tensor:

@@ -6,11 +6,11 @@ import torch
 from oracle import igr_ref as ref
 
 
-def problem_from(w, nsweeps=None, alpha=None):
+def problem_from(w, nsweeps=None, alpha=None, order=5):
     patches = tuple(ref.Patch(j.yc, j.zc, j.r, j.rho, j.ux, j.uy, j.uz, j.p, j.width) for j in w.jets)
     return ref.Problem(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, gamma=w.gamma,
                        alpha=w.alpha if alpha is None else alpha, faces=tuple(w.faces),
-                       patches=patches, nsweeps=w.nsweeps if nsweeps is None else nsweeps)
+                       patches=patches, nsweeps=w.nsweeps if nsweeps is None else nsweeps, order=order)
 
 
 def state_of(w):

@@ -71,7 +71,7 @@ def test_init_rejects_bad_arguments(case, code):
     elif case == "precision":
         opts = igr.Opts(7, 5, 5, 0)
     elif case == "order":
-        opts = igr.Opts(0, 3, 5, 0)
+        opts = igr.Opts(0, 4, 5, 0)
     elif case == "sweeps":
         opts = igr.Opts(0, 5, -1, 0)
     elif case == "spacing":

@@ -217,3 +217,15 @@ def test_gradient_workload_128_against_finite_differences(plane):
 
 def Solver_interior(a):
     return igr.Solver.interior(a)
+
+
+def test_adjoint_rejects_third_order():
+    """The hand-written adjoint covers fifth-order reconstruction only; a
+    third-order context reports IGR_EUNSUPPORTED instead of a wrong result."""
+    w = _case()
+    s = igr.Solver.from_workload(w, order=3)
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    with pytest.raises(igr.IGRError) as e:
+        s.rhs_adjoint(U, sig, torch.zeros_like(U), torch.zeros_like(sig))
+    assert e.value.code == igr.IGR_EUNSUPPORTED
