@@ -27,10 +27,14 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2505_07392_amd", "csrc")
 
 
-def sigma_schedule(nsweeps: int, precision: str, sigma_block: int = 0):
+def sigma_schedule(nsweeps: int, precision: str, sigma_block: int = 0, smoother: str = "jacobi"):
     """Launches of one Sigma solve as the library runs them: (first sweep,
     two-sweep passes, later single sweeps).  The default (0) is two-sweep
-    passes in FP64 and single sweeps in the forms with FP32 arithmetic."""
+    passes in FP64 and single sweeps in the forms with FP32 arithmetic.
+    Red-black Gauss-Seidel runs two in-place half-sweeps per sweep, each
+    counted here as a single sweep."""
+    if smoother == "rbgs":
+        return (1, 0, 2 * nsweeps - 1) if nsweeps else (0, 0, 0)
     sb = sigma_block or (2 if precision == "f64" else 1)
     if sb > 2:
         raise ValueError("the fused-source march passes are not modelled here")
@@ -42,7 +46,7 @@ def sigma_schedule(nsweeps: int, precision: str, sigma_block: int = 0):
 
 
 def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int, precision: str = "f64",
-                               sigma_block: int = 0) -> float:
+                               sigma_block: int = 0, smoother: str = "jacobi") -> float:
     """Compulsory HBM bytes per interior cell for one launch of `kernel`
     (averaged over the launches of one right-hand side)."""
     if kernel == "flux_rk":
@@ -51,7 +55,7 @@ def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int
     if kernel == "jacobi":
         # first sweep: reads rho, m, Sigma; writes Sigma, b.  Later sweeps,
         # single or two per pass: read Sigma, rho, b; write Sigma
-        nf, npair, nsingle = sigma_schedule(nsweeps, precision, sigma_block)
+        nf, npair, nsingle = sigma_schedule(nsweeps, precision, sigma_block, smoother)
         first = 5 * esize + esize + csize
         later = 3 * esize + csize
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
@@ -62,7 +66,7 @@ def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int
     raise KeyError(kernel)
 
 
-def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int = 0):
+def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int = 0, smoother: str = "jacobi"):
     """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
     Sigma kernels from their measured average launch time."""
     esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
@@ -71,7 +75,7 @@ def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: 
     for k in ("flux_rk", "jacobi"):
         ms, cnt = kt[k]
         if cnt:
-            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, precision, sigma_block) * cells
+            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, precision, sigma_block, smoother) * cells
             gbs = ab / (ms / cnt / 1e3) / 1e9
             out[k] = {"avg_ms": round(ms / cnt, 5), "launches": cnt, "achieved_GBs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -124,12 +128,12 @@ def cpu_baseline(w, seconds_target: float = 15.0):
                       f"seed as the 256^3 workload), {el:.1f} s"}
 
 
-def run_form(w, precision, steps, warmup, sigma_block=0, order=5):
+def run_form(w, precision, steps, warmup, sigma_block=0, order=5, smoother="jacobi"):
     import torch
 
     from paper_2505_07392_amd import igr
 
-    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block, order=order)
+    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block, order=order, smoother=smoother)
     U = s.state_from(w.U)
     sig = s.new_field()
     for _ in range(warmup):
@@ -244,6 +248,7 @@ def main():
     ap.add_argument("--sigma-block", type=int, default=0, choices=[0, 1, 2],
                     help="Sigma pass structure: 1 single sweeps, 2 two-sweep passes (0: library default)")
     ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "rbgs"], help="Sigma sweeps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -282,7 +287,7 @@ def main():
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
     csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 
-    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order)
+    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
     value = cells * args.steps / el
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -290,12 +295,13 @@ def main():
     avg_s = ms / count / 1e3
     try:
         abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps,
-                                            args.precision, args.sigma_block) * cells
+                                            args.precision, args.sigma_block, args.smoother) * cells
     except KeyError:
         abytes = None
     workload = f"periodic_box_{args.n}"
     achieved = abytes / avg_s / 1e9 if abytes else None
-    traffic = load_traffic(dom, f"{workload}_{args.precision}") if args.order == 5 and not args.sigma_block else None
+    traffic = load_traffic(dom, f"{workload}_{args.precision}") if (args.order == 5 and not args.sigma_block
+                                                                      and args.smoother == "jacobi") else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                 "avg_launch_ms": ms / count, "launches": count,
@@ -306,16 +312,16 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x and x != args.precision]:
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order)
+        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
         forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
                     "vs_f64": None}
-        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, args.sigma_block))
+        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, args.sigma_block, args.smoother))
 
     if args.precision == "f64":
         for f in forms:
             forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
     kernels.update({k + "_roofline": v for k, v in kernel_rooflines(kt, cells, args.precision, w.nsweeps,
-                                                                    args.sigma_block).items()})
+                                                                    args.sigma_block, args.smoother).items()})
     line = {
         "metric": "cell-updates/s per RK3 step (incl. Sigma Jacobi)",
         "value": value,
@@ -332,7 +338,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{workload} periodic box {args.n}^3, rms Mach 1.5, alpha=dx^2, "
                                f"{w.nsweeps} Jacobi sweeps, CFL 0.5", "cells": cells,
-                   "sweeps": w.nsweeps, "precision": args.precision, "order": args.order},
+                   "sweeps": w.nsweeps, "precision": args.precision, "order": args.order,
+                   "smoother": args.smoother},
         "roofline": roofline,
         "kernels": kernels,
         "forms": forms,

@@ -77,6 +77,8 @@ enum { IGR_BC_PERIODIC = 0, IGR_BC_EXTRAP = 1 };
 
 enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2, IGR_F16_F32 = 3 };
 
+enum { IGR_SMOOTH_JACOBI = 0, IGR_SMOOTH_RBGS = 1 };
+
 /* Uniform rectilinear grid of nx*ny*nz interior cells with spacings dx, dy,
  * dz (paper, "Example simulation result": rectilinear grid).  Each extent
  * must be >= 1; ghost indices wrap modulo the extent on periodic axes. */
@@ -121,12 +123,19 @@ typedef struct {
  * two sweeps per pass (temporally blocked, reusing the stored source);
  * 3..5 run passes of up to that many sweeps of a kernel that forms the
  * source itself.  0 selects the default: 2 for IGR_F64, 1 for the forms
- * with FP32 arithmetic.  Results agree to rounding. */
+ * with FP32 arithmetic.  Results agree to rounding.  smoother selects the
+ * sweep: IGR_SMOOTH_JACOBI (default), or IGR_SMOOTH_RBGS, red-black
+ * Gauss-Seidel (the paper's alternative, "Discretization"): each sweep
+ * updates the cells with i + j + k even, then the others, in place, each
+ * colour from the values at the start of its half-sweep (sigma_block is
+ * then ignored; periodic axes need even extents, else IGR_EUNSUPPORTED;
+ * the adjoint entry points need Jacobi). */
 typedef struct {
     int32_t precision;
     int32_t order;
     int32_t nsweeps;
     int32_t sigma_block;
+    int32_t smoother;
 } igr_opts;
 
 typedef struct igr_ctx igr_ctx;

@@ -58,6 +58,7 @@ struct igr_ctx {
     int precision = IGR_F64;
     int nsweeps = 5;
     int order = 5;         // reconstruction order (5 or 3)
+    int smoother = IGR_SMOOTH_JACOBI;
     int sigma_block = 1;   // Sigma pass structure (1: single sweeps, 2: first + two-sweep passes, 3..5: fused march)
     int faces[6] = {0, 0, 0, 0, 0, 0};
     int device = 0;
@@ -267,7 +268,7 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         src = dst;
         dst = tmp;
     };
-    if (c->sigma_block <= 2) {
+    if (c->sigma_block <= 2 || c->smoother == IGR_SMOOTH_RBGS) {
         const Geom& g = c->g;
         const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + SWEEP_RY - 1) / SWEEP_RY;
         const long long tiles = (long long)tiles_x * tiles_y;
@@ -285,16 +286,26 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
         C* b = static_cast<C*>(c->d_b);
         C* ir = static_cast<C*>(c->d_ir);
-        auto single = [&](bool first) {
+        auto single = [&](bool first, int colour = -1) {
+            T* out = colour < 0 ? dst : src;   // red-black half-sweeps work in place
             return launch(c, K_JACOBI, s, [&] {
                 if (first)
-                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
-                                                                                             int(zc), tiles_x, tiles_y);
+                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(
+                        U, src, out, b, ir, g, int(zc), tiles_x, tiles_y, colour);
                 else
-                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(U, src, dst, b, ir, g,
-                                                                                              int(zc), tiles_x, tiles_y);
+                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(
+                        U, src, out, b, ir, g, int(zc), tiles_x, tiles_y, colour);
             });
         };
+        if (c->smoother == IGR_SMOOTH_RBGS) {
+            // red-black Gauss-Seidel: red half (the first also forms b), then black
+            for (int it = 0; it < nsweeps; ++it) {
+                IGR_TRY(single(it == 0, 0));
+                IGR_TRY(single(false, 1));
+            }
+            *result = src;
+            return fill_sigma_ghosts(c, src, s);
+        }
         int left = nsweeps;
         if (left > 0) {
             IGR_TRY(single(true));
@@ -792,6 +803,14 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
         return fail(IGR_EUNSUPPORTED, "reconstruction order must be 5 or 3");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
     if (opts->sigma_block < 0 || opts->sigma_block > 5) return fail(IGR_EINVAL, "sigma_block must be in 0..5");
+    if (opts->smoother != IGR_SMOOTH_JACOBI && opts->smoother != IGR_SMOOTH_RBGS)
+        return fail(IGR_EINVAL, "unknown smoother");
+    if (opts->smoother == IGR_SMOOTH_RBGS) {
+        const int ext[3] = {grid->nx, grid->ny, grid->nz};
+        for (int d = 0; d < 3; ++d)
+            if (bc->face[2 * d] == IGR_BC_PERIODIC && (ext[d] & 1))
+                return fail(IGR_EUNSUPPORTED, "red-black Gauss-Seidel needs even extents on periodic axes");
+    }
 
     igr_ctx* c = new (std::nothrow) igr_ctx();
     if (!c) return fail(IGR_ENOMEM, "host allocation failed");
@@ -804,6 +823,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->precision = opts->precision;
     c->nsweeps = opts->nsweeps;
     c->order = opts->order;
+    c->smoother = opts->smoother;
     // default: two sweeps per pass where the arithmetic is FP64 (the
     // sweeps are then bound by memory), single sweeps otherwise (FP32
     // arithmetic on 2- or 4-byte storage: the single-sweep kernel is faster)
@@ -980,6 +1000,7 @@ int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* r
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
+    if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
     // inputs may alias outputs: stage them
@@ -1005,6 +1026,7 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
+    if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
     if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));

@@ -283,7 +283,8 @@ __device__ __forceinline__ C jacobi_point(C bk, C ic, const C (&ir)[6], const C 
 // enough bytes are in flight per CU to cover HBM latency.  With FIRST the
 // source b is formed in the same pass (from rho and m) and written for the
 // later sweeps.  Per cell: FIRST reads rho, m, Sigma and writes Sigma, b;
-// later sweeps read Sigma, rho, b and write Sigma.
+// later sweeps read Sigma, rho, b and write Sigma.  With colour >= 0 the
+// kernel runs one half of a red-black Gauss-Seidel sweep in place.
 // Loads of one iteration of the single-sweep kernel.  The own-column values
 // of plane k+1 (which miss to HBM) are fetched PD iterations ahead; the x/y
 // neighbours of plane k (mostly L1/L2 hits: other threads' columns) one
@@ -312,10 +313,10 @@ struct SweepNb {
 constexpr int SWEEP_RY = IGR_SWEEP_RY;   // rows of a sweep block (64 x SWEEP_RY columns)
 
 template <class T, bool FIRST>
-__global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__ U, const T* __restrict__ Sin,
-                                                 T* __restrict__ Sout, typename Storage<T>::C* __restrict__ b,
+__global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__ U, const T* Sin, T* Sout,
+                                                 typename Storage<T>::C* __restrict__ b,
                                                  typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
-                                                 int tiles_x, int tiles_y) {
+                                                 int tiles_x, int tiles_y, int colour) {
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
@@ -458,7 +459,12 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
         }
         const C irv[6] = {irn[0], irn[1], irn[2], irn[3], ir_m, ir_p};
         const C sgv[6] = {S::cvt(cur.sig[0]), S::cvt(cur.sig[1]), S::cvt(cur.sig[2]), S::cvt(cur.sig[3]), s_m, s_p};
-        S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, alpha, hx2, hy2, hz2));
+        // colour < 0: every cell (Jacobi, Sout != Sin); else only the cells
+        // with (i + j + k) % 2 == colour, in place (red-black Gauss-Seidel:
+        // with even periodic extents every neighbour read here has the
+        // other colour, so no value this launch writes is read by it)
+        if (colour < 0 || ((i + j + k) & 1) == colour)
+            S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, alpha, hx2, hy2, hz2));
         ir_m = ir_c;
         ir_c = ir_p;
         s_m = s_c;

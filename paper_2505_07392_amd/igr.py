@@ -22,6 +22,7 @@ IGR_OK, IGR_EINVAL, IGR_ENOMEM, IGR_EHIP, IGR_ENONFINITE, IGR_EUNSUPPORTED = ran
 BC_KIND = {"periodic": 0, "extrap": 1}
 PRECISION = {"f64": (0, torch.float64), "f32": (1, torch.float32), "bf16": (2, torch.bfloat16),
              "f16": (3, torch.float16)}
+SMOOTHER = {"jacobi": 0, "rbgs": 1}
 
 
 class Grid(ctypes.Structure):
@@ -39,7 +40,7 @@ class BC(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("nsweeps", ctypes.c_int32), ("sigma_block", ctypes.c_int32)]
+                ("nsweeps", ctypes.c_int32), ("sigma_block", ctypes.c_int32), ("smoother", ctypes.c_int32)]
 
 
 class IGRError(RuntimeError):
@@ -121,7 +122,8 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, *, gamma: float = 1.4,
                  alpha: float = 0.0, faces: Sequence[str] = ("extrap",) * 6, jets: Iterable = (),
-                 nsweeps: int = 5, precision: str = "f64", sigma_block: int = 0, order: int = 5, device=None):
+                 nsweeps: int = 5, precision: str = "f64", sigma_block: int = 0, order: int = 5,
+                 smoother: str = "jacobi", device=None):
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {list(PRECISION)}")
         self.nx, self.ny, self.nz = nx, ny, nz
@@ -138,8 +140,10 @@ class Solver:
         for i, j in enumerate(jets):
             self._patches[i] = Patch(j.yc, j.zc, j.r, getattr(j, "width", 0.0), j.rho, j.ux, j.uy, j.uz, j.p)
         bc = BC((ctypes.c_int32 * 6)(*[BC_KIND[f] for f in faces]), len(jets), self._patches)
-        self.order = order
-        opts = Opts(PRECISION[precision][0], order, nsweeps, sigma_block)
+        if smoother not in SMOOTHER:
+            raise ValueError(f"smoother must be one of {list(SMOOTHER)}")
+        self.order, self.smoother = order, smoother
+        opts = Opts(PRECISION[precision][0], order, nsweeps, sigma_block, SMOOTHER[smoother])
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().igr_init(ctypes.byref(Grid(nx, ny, nz, dx, dy, dz)), gamma, alpha, ctypes.byref(bc),
@@ -148,10 +152,10 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, precision: str = "f64", nsweeps: Optional[int] = None, sigma_block: int = 0,
-                      order: int = 5, device=None) -> "Solver":
+                      order: int = 5, smoother: str = "jacobi", device=None) -> "Solver":
         return cls(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha, faces=tuple(w.faces),
                    jets=w.jets, nsweeps=w.nsweeps if nsweeps is None else nsweeps, precision=precision,
-                   sigma_block=sigma_block, order=order, device=device)
+                   sigma_block=sigma_block, order=order, smoother=smoother, device=device)
 
     # -- memory ------------------------------------------------------------
     def new_state(self) -> torch.Tensor:

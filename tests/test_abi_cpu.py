@@ -55,6 +55,7 @@ def _init(grid, gamma, alpha, bc, opts):
     ("null", igr.IGR_EINVAL), ("gamma", igr.IGR_EINVAL), ("alpha", igr.IGR_EINVAL), ("extent", igr.IGR_EINVAL),
     ("pair", igr.IGR_EINVAL), ("precision", igr.IGR_EINVAL), ("order", igr.IGR_EUNSUPPORTED),
     ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("sigma_block", igr.IGR_EINVAL),
+    ("smoother", igr.IGR_EINVAL), ("rbgs_odd_periodic", igr.IGR_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_arguments(case, code):
     grid, bc, opts, gamma, alpha = _grid(), _bc(), igr.Opts(0, 5, 5, 0), 1.4, 0.01
@@ -78,6 +79,12 @@ def test_init_rejects_bad_arguments(case, code):
         grid = igr.Grid(8, 8, 8, 0.0, 0.1, 0.1)
     elif case == "sigma_block":
         opts = igr.Opts(0, 5, 5, 9)
+    elif case == "smoother":
+        opts = igr.Opts(0, 5, 5, 0, 2)
+    elif case == "rbgs_odd_periodic":
+        grid = igr.Grid(8, 7, 8, 0.1, 0.1, 0.1)
+        bc = igr.BC((ctypes.c_int32 * 6)(1, 1, 0, 0, 1, 1), 0, None)
+        opts = igr.Opts(0, 5, 5, 0, 1)
     rc, h = _init(grid, gamma, alpha, bc, opts)
     assert rc == code
     assert h.value is None

@@ -229,3 +229,13 @@ def test_adjoint_rejects_third_order():
     with pytest.raises(igr.IGRError) as e:
         s.rhs_adjoint(U, sig, torch.zeros_like(U), torch.zeros_like(sig))
     assert e.value.code == igr.IGR_EUNSUPPORTED
+
+
+def test_adjoint_rejects_red_black():
+    w = _case(ny=10)
+    s = igr.Solver.from_workload(w, smoother="rbgs")
+    U = s.state_from(w.U)
+    sig = s.new_field()
+    with pytest.raises(igr.IGRError) as e:
+        s.rhs_adjoint(U, sig, torch.zeros_like(U), torch.zeros_like(sig))
+    assert e.value.code == igr.IGR_EUNSUPPORTED
