@@ -270,31 +270,44 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
     };
     if (c->sigma_block <= 2 || c->smoother == IGR_SMOOTH_RBGS) {
         const Geom& g = c->g;
-        const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + SWEEP_RY - 1) / SWEEP_RY;
-        const long long tiles = (long long)tiles_x * tiles_y;
 #ifndef IGR_SWEEP_BLOCKS
 #define IGR_SWEEP_BLOCKS 2048
 #endif
 #ifndef IGR_SWEEP_ZC_MIN
 #define IGR_SWEEP_ZC_MIN 4
 #endif
-        long long zc = (tiles * g.n[2] + IGR_SWEEP_BLOCKS - 1) / IGR_SWEEP_BLOCKS;
-        if (zc < IGR_SWEEP_ZC_MIN) zc = IGR_SWEEP_ZC_MIN;
-        if (zc > 64) zc = 64;
-        if (zc > g.n[2]) zc = g.n[2];
-        const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
-        if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
+        // 64 x ry column tiles, z chunks sized for about IGR_SWEEP_BLOCKS blocks
+        struct Shape {
+            int tiles_x, tiles_y, zc;
+            long long blocks;
+        };
+        auto shape = [&](int ry) {
+            Shape sh;
+            sh.tiles_x = (g.n[0] + 63) / 64;
+            sh.tiles_y = (g.n[1] + ry - 1) / ry;
+            const long long tiles = (long long)sh.tiles_x * sh.tiles_y;
+            long long zc = (tiles * g.n[2] + IGR_SWEEP_BLOCKS - 1) / IGR_SWEEP_BLOCKS;
+            if (zc < IGR_SWEEP_ZC_MIN) zc = IGR_SWEEP_ZC_MIN;
+            if (zc > 64) zc = 64;
+            if (zc > g.n[2]) zc = g.n[2];
+            sh.zc = int(zc);
+            sh.blocks = tiles * ((g.n[2] + zc - 1) / zc);
+            return sh;
+        };
+        const Shape sf = shape(SWEEP_RY_FIRST), sl = shape(SWEEP_RY);
+        if (sf.blocks > 0x7fffffffLL || sl.blocks > 0x7fffffffLL)
+            return fail(IGR_EINVAL, "grid too large for the sweep launch");
         C* b = static_cast<C*>(c->d_b);
         C* ir = static_cast<C*>(c->d_ir);
         auto single = [&](bool first, int colour = -1) {
             T* out = colour < 0 ? dst : src;   // red-black half-sweeps work in place
             return launch(c, K_JACOBI, s, [&] {
                 if (first)
-                    k_sweep_z<T, true><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(
-                        U, src, out, b, ir, g, int(zc), tiles_x, tiles_y, colour);
+                    k_sweep_z<T, true, SWEEP_RY_FIRST><<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
+                        U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour);
                 else
-                    k_sweep_z<T, false><<<dim3(unsigned(blocks)), dim3(64, SWEEP_RY), 0, s>>>(
-                        U, src, out, b, ir, g, int(zc), tiles_x, tiles_y, colour);
+                    k_sweep_z<T, false, SWEEP_RY><<<dim3(unsigned(sl.blocks)), dim3(64, SWEEP_RY), 0, s>>>(
+                        U, src, out, b, ir, g, sl.zc, sl.tiles_x, sl.tiles_y, colour);
             });
         };
         if (c->smoother == IGR_SMOOTH_RBGS) {

@@ -310,10 +310,14 @@ struct SweepNb {
 #ifndef IGR_SWEEP_RY
 #define IGR_SWEEP_RY 4
 #endif
-constexpr int SWEEP_RY = IGR_SWEEP_RY;   // rows of a sweep block (64 x SWEEP_RY columns)
+#ifndef IGR_SWEEP_RY_FIRST
+#define IGR_SWEEP_RY_FIRST 4
+#endif
+constexpr int SWEEP_RY = IGR_SWEEP_RY;               // rows of a later-sweep block (64 x SWEEP_RY)
+constexpr int SWEEP_RY_FIRST = IGR_SWEEP_RY_FIRST;   // rows of a first-sweep block
 
-template <class T, bool FIRST>
-__global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__ U, const T* Sin, T* Sout,
+template <class T, bool FIRST, int RY>
+__global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, const T* Sin, T* Sout,
                                                  typename Storage<T>::C* __restrict__ b,
                                                  typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
                                                  int tiles_x, int tiles_y, int colour) {
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
     const int by = bidx % tiles_y;
     const int bz = bidx / tiles_y;
     const int i = bx * 64 + threadIdx.x;
-    const int j = by * SWEEP_RY + threadIdx.y;
+    const int j = by * RY + threadIdx.y;
     const int z0 = bz * zc;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     if (i >= nx || j >= ny) return;
@@ -403,18 +407,24 @@ __global__ __launch_bounds__(64 * SWEEP_RY) void k_sweep_z(const T* __restrict__
             u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
         }
     }
+    // Loads are unconditional (planes clamped to the chunk) and issued in
+    // the order they are needed -- the neighbours of the next plane first,
+    // then the own column PD planes ahead -- because vector-memory counters
+    // complete in order: waiting for the neighbours must not wait for the
+    // look-ahead.  The loop is unrolled over the register rotation so that
+    // the rotation is renaming, not copies of pending loads.
     SweepCol<T, FIRST> q[PD];   // own columns for iterations k .. k+PD-1
 #pragma unroll
-    for (int d = 0; d < PD; ++d)
-        if (z0 + d < z1) load_col(z0 + d, q[d]);
+    for (int d = 0; d < PD; ++d) load_col(min(z0 + d, z1 - 1), q[d]);
     SweepNb<T, FIRST> cur, nxt;
     load_nb(z0, cur);
+#pragma unroll 6
     for (int k = z0; k < z1; ++k) {
         const SweepCol<T, FIRST> cc = q[0];
 #pragma unroll
         for (int d = 0; d < PD - 1; ++d) q[d] = q[d + 1];
-        if (k + PD < z1) load_col(k + PD, q[PD - 1]);
-        if (k + 1 < z1) load_nb(k + 1, nxt);
+        load_nb(min(k + 1, z1 - 1), nxt);
+        load_col(min(k + PD, z1 - 1), q[PD - 1]);
         const long long o = zplane(k);
         const C ir_p = inv_rho(cc.rho);
         const C s_p = S::cvt(cc.sig);
