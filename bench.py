@@ -2,7 +2,9 @@
 
 A step is one SSP-RK3 step of the whole path (three right-hand sides, each
 with its ghost fill, Sigma source, Jacobi sweeps and fused reconstruction +
-LLF flux + divergence + stage update, plus the FP64 CFL reduction) over the
+LLF flux + divergence + stage update, plus the FP64 CFL reduction; the
+timed steps run through igr_advance, which fuses each later step's CFL
+maximum into the previous step's last stage) over the
 256^3 periodic box (rho = 1 + 0.2 * Gaussian-smoothed noise, solenoidal
 k^-2 velocity at rms Mach 1.5, p = 1, alpha = dx^2, 5 sweeps, CFL 0.5),
 with the state resident in HBM.
@@ -136,14 +138,12 @@ def run_form(w, precision, steps, warmup, sigma_block=0, order=5, smoother="jaco
     s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block, order=order, smoother=smoother)
     U = s.state_from(w.U)
     sig = s.new_field()
-    for _ in range(warmup):
-        s.step(U, sig, cfl=w.cfl, sync=False)
+    s.advance(U, sig, warmup, cfl=w.cfl, sync=False)
     s.check()
     torch.cuda.synchronize()
     s.timing(True)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        s.step(U, sig, cfl=w.cfl, sync=False)
+    s.advance(U, sig, steps, cfl=w.cfl, sync=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     s.timing(False)
@@ -188,13 +188,11 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
             out["dt"] = dt
         free, total = torch.cuda.mem_get_info()
         print(f"[bench] multi-jet {n}^3 {prec}: timing", file=sys.stderr, flush=True)
-        for _ in range(warmup):
-            s.step(U, S, dt_fixed=dt, sync=False)
+        s.advance(U, S, warmup, dt_fixed=dt, sync=False)
         torch.cuda.synchronize()
         s.timing(True)
         t0 = time.perf_counter()
-        for _ in range(timed_steps):
-            s.step(U, S, dt_fixed=dt, sync=False)
+        s.advance(U, S, timed_steps, dt_fixed=dt, sync=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         s.timing(False)

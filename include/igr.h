@@ -186,6 +186,17 @@ int igr_rhs(igr_ctx *ctx, void *U, void *sigma, void *rhs, void *stream);
 int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, double *dt_used,
              void *stream);
 
+/* nsteps igr_step calls in one: the same states and time steps.  With a
+ * CFL time step (dt_fixed <= 0) the maximum speed for step n+1 is formed
+ * by step n's last stage as it writes the new state (the same FP64
+ * expression as the standalone reduction, on the values as stored), so the
+ * separate pass over U runs only before the first step; in IGR_F64 the
+ * separate pass runs before every step (the fused form does not pay there).  If dt_last is not
+ * NULL the stream is synchronised, *dt_last receives the last step's dt
+ * and the error flag is checked.  nsteps >= 0. */
+int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,
+                void *stream);
+
 /* Discrete adjoint of igr_rhs (FP64 contexts with fifth-order
  * reconstruction, else IGR_EUNSUPPORTED; vector-Jacobian product of
  * the map (U, sigma_prev) -> (L(U), sigma_new) and of the jet-disc

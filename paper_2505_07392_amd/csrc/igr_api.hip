@@ -76,6 +76,7 @@ struct igr_ctx {
     void* d_ir = nullptr;         // 1/rho written by the first sweep (FP64)
     double* d_partial = nullptr;
     double* d_scalars = nullptr;  // [0] dt, [1..5] sums, [6] residual
+    double* d_speed = nullptr;    // per-flux-block CFL maxima left by a step's last stage
     int* d_flag = nullptr;
     bool timing = false;
     std::vector<TimingRecord> records;
@@ -140,28 +141,19 @@ dim3 cell_grid(const Geom& g) { return dim3((g.n[0] + 63) / 64, (g.n[1] + 3) / 4
 
 template <class T>
 int fill_state_ghosts(igr_ctx* c, T* U, hipStream_t s) {
-    for (int axis = 0; axis < 3; ++axis) {
-        const int a = axis == 0 ? 1 : 0;
-        const int b = axis == 2 ? 1 : 2;
-        const long long tot = 2LL * c->g.n[a] * c->g.n[b];
-        const int blocks = int((tot + 255) / 256);
-        const bool inflow = axis == 0 && !c->patches.empty();
-        IGR_TRY(launch(c, K_BC_STATE, s, [&] {
-            k_bc_state<T><<<blocks, 256, 0, s>>>(U, c->g, axis, inflow ? c->d_owner : nullptr, c->d_chi, c->d_jet);
-        }));
-    }
+    const long long tot = bc_face_threads(c->g);
+    if (tot / 256 + 1 > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the ghost fill");
+    const int blocks = int((tot + 255) / 256);
+    const int* owner = c->patches.empty() ? nullptr : c->d_owner;
+    IGR_TRY(launch(c, K_BC_STATE, s, [&] { k_bc_state<T><<<blocks, 256, 0, s>>>(U, c->g, owner, c->d_chi, c->d_jet); }));
     return IGR_OK;
 }
 
 template <class T>
 int fill_sigma_ghosts(igr_ctx* c, T* Sg, hipStream_t s) {
-    for (int axis = 0; axis < 3; ++axis) {
-        const int a = axis == 0 ? 1 : 0;
-        const int b = axis == 2 ? 1 : 2;
-        const long long tot = 2LL * c->g.n[a] * c->g.n[b];
-        const int blocks = int((tot + 255) / 256);
-        IGR_TRY(launch(c, K_BC_SIGMA, s, [&] { k_bc_sigma<T><<<blocks, 256, 0, s>>>(Sg, c->g, axis); }));
-    }
+    const long long tot = bc_face_threads(c->g);
+    const int blocks = int((tot + 255) / 256);
+    IGR_TRY(launch(c, K_BC_SIGMA, s, [&] { k_bc_sigma<T><<<blocks, 256, 0, s>>>(Sg, c->g); }));
     return IGR_OK;
 }
 
@@ -417,18 +409,24 @@ FluxLaunch flux_launch(const Geom& g, int ty, int target_blocks) {
 
 template <class T, int MODE>
 int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
-              hipStream_t s) {
+              hipStream_t s, double* speed = nullptr) {
     constexpr int TY = FluxShape<T>::TY;
     const FluxLaunch L = flux_launch(c->g, TY, FluxShape<T>::BLOCKS);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
         if (c->order == 3)
             k_flux_tiled<T, MODE, TY, 3><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed);
         else
             k_flux_tiled<T, MODE, TY, 5><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc);
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed);
     });
+}
+
+// blocks of one flux launch (the length of the fused CFL maxima)
+template <class T>
+long long flux_blocks(const igr_ctx* c) {
+    return flux_launch(c->g, FluxShape<T>::TY, FluxShape<T>::BLOCKS).blocks();
 }
 
 template <class T>
@@ -459,13 +457,11 @@ int rhs_impl(igr_ctx* c, T* U, T* sig, T* rhs, hipStream_t s) {
     return flux_impl<T, MODE_RHS>(c, U, sig, nullptr, rhs, nullptr, 0.0, s);
 }
 
+// The three RK stages of one step with the time step at *dtp (device) or
+// dt_fixed; with `speed` the last stage also leaves the per-block CFL
+// maxima of the new state there (one value per flux block).
 template <class T>
-int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t s) {
-    const double* dtp = nullptr;
-    if (!(dt_fixed > 0.0)) {
-        IGR_TRY(speed_dt_impl(c, U, cfl, s));
-        dtp = c->d_scalars;
-    }
+int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hipStream_t s, double* speed) {
     T* Ua = static_cast<T*>(c->d_Ua);
     T* Ub = static_cast<T*>(c->d_Ub);
     // Sigma ping-pongs between the caller's buffer and the scratch copy
@@ -492,8 +488,46 @@ int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t
     // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un
     IGR_TRY(fill_state_ghosts(c, Ub, s));
     IGR_TRY(solve(Ub));
-    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s)));
+    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s, speed)));
     if (cur != sig) IGR_HIP(hipMemcpyAsync(sig, cur, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
+    return IGR_OK;
+}
+
+template <class T>
+int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t s) {
+    const double* dtp = nullptr;
+    if (!(dt_fixed > 0.0)) {
+        IGR_TRY(speed_dt_impl(c, U, cfl, s));
+        dtp = c->d_scalars;
+    }
+    return step_stages(c, U, sig, dtp, dt_fixed, s, nullptr);
+}
+
+// nsteps steps; with a CFL time step, the first step's maximum comes from
+// the standalone reduction and every later one from the maxima that the
+// previous step's last stage left in d_speed.  The fusion is compiled for
+// the forms with FP32 arithmetic only (the FP64 flux kernel is at its
+// register limit, and spilling there costs what the separate pass does):
+// FP64 runs the standalone reduction before every step.
+template <class T>
+int advance_impl(igr_ctx* c, T* U, T* sig, int nsteps, double cfl, double dt_fixed, hipStream_t s) {
+    const bool use_cfl = !(dt_fixed > 0.0);
+    constexpr bool fused = sizeof(typename Storage<T>::C) == 4;
+    const int nblk = int(flux_blocks<T>(c));
+    for (int n = 0; n < nsteps; ++n) {
+        const double* dtp = nullptr;
+        if (use_cfl) {
+            if (n == 0 || !fused) {
+                IGR_TRY(speed_dt_impl(c, U, cfl, s));
+            } else {
+                IGR_TRY(launch(c, K_DT, s, [&] {
+                    k_dt_final<<<1, RED_THREADS, 0, s>>>(c->d_speed, nblk, cfl, c->d_scalars);
+                }));
+            }
+            dtp = c->d_scalars;
+        }
+        IGR_TRY(step_stages(c, U, sig, dtp, dt_fixed, s, fused && use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
+    }
     return IGR_OK;
 }
 
@@ -574,7 +608,8 @@ int upload_jets(igr_ctx* c, hipStream_t s, bool sync) {
 
 void release(igr_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_owner, c->d_chi, c->d_jet, c->d_Ua, c->d_Ub, c->d_sig2, c->d_b, c->d_ir, c->d_partial, c->d_scalars, c->d_flag};
+    void* ptrs[] = {c->d_owner, c->d_chi,     c->d_jet,     c->d_Ua,   c->d_Ub,   c->d_sig2,
+                    c->d_b,     c->d_ir,      c->d_partial, c->d_scalars, c->d_flag, c->d_speed};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (double* p : c->adj)
@@ -603,6 +638,10 @@ int rhs_t(igr_ctx* c, void* U, void* sig, void* rhs, hipStream_t s) {
 template <class T>
 int step_t(igr_ctx* c, void* U, void* sig, double cfl, double dt_fixed, hipStream_t s) {
     return step_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), cfl, dt_fixed, s);
+}
+template <class T>
+int advance_t(igr_ctx* c, void* U, void* sig, int nsteps, double cfl, double dt_fixed, hipStream_t s) {
+    return advance_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), nsteps, cfl, dt_fixed, s);
 }
 template <class T>
 int sigma_t(igr_ctx* c, void* U, void* sig, int nsweeps, double* resid, hipStream_t s) {
@@ -881,6 +920,10 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
+    if (!rc) {
+        const long long nb = c->precision == IGR_F64 ? flux_blocks<double>(c) : flux_blocks<float>(c);
+        rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
+    }
     if (!rc && !c->patches.empty()) {
         const size_t cols = (size_t)c->ny * c->nz;
         rc = alloc((void**)&c->d_owner, cols * sizeof(int));
@@ -956,6 +999,24 @@ int igr_step(igr_ctx* ctx, void* U, void* sigma, double cfl, double dt_fixed, do
             *dt_used = dt_fixed;
         } else {
             IGR_HIP(hipMemcpyAsync(dt_used, ctx->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        return read_flag(ctx, s);
+    }
+    return IGR_OK;
+}
+
+int igr_advance(igr_ctx* ctx, void* U, void* sigma, int32_t nsteps, double cfl, double dt_fixed, double* dt_last,
+                void* stream) {
+    if (!ctx || !U || !sigma) return fail(IGR_EINVAL, "null argument");
+    if (nsteps < 0) return fail(IGR_EINVAL, "nsteps must be >= 0");
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(IGR_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(DISPATCH(ctx, advance_t, ctx, U, sigma, nsteps, cfl, dt_fixed, s));
+    if (dt_last) {
+        if (dt_fixed > 0.0 || nsteps == 0) {
+            *dt_last = dt_fixed > 0.0 ? dt_fixed : 0.0;
+        } else {
+            IGR_HIP(hipMemcpyAsync(dt_last, ctx->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         }
         return read_flag(ctx, s);
     }

@@ -36,6 +36,7 @@ struct Storage<double> {
     __device__ __forceinline__ static C cvt(R r) { return r; }
     __device__ __forceinline__ static double load(const double* p) { return *p; }
     __device__ __forceinline__ static void store(double* p, double v) { *p = v; }
+    __device__ __forceinline__ static C stored(C v) { return v; }   // value as read back after a store
 };
 
 template <>
@@ -46,6 +47,7 @@ struct Storage<float> {
     __device__ __forceinline__ static C cvt(R r) { return r; }
     __device__ __forceinline__ static float load(const float* p) { return *p; }
     __device__ __forceinline__ static void store(float* p, float v) { *p = v; }
+    __device__ __forceinline__ static C stored(C v) { return v; }
 };
 
 template <>
@@ -56,6 +58,7 @@ struct Storage<bf16> {
     __device__ __forceinline__ static C cvt(R r) { return __uint_as_float(r << 16); }
     __device__ __forceinline__ static float load(const bf16* p) { return cvt(load_raw(p)); }
     __device__ __forceinline__ static void store(bf16* p, float v) { p->bits = f32_to_bf16_rne(v); }
+    __device__ __forceinline__ static C stored(C v) { return cvt(f32_to_bf16_rne(v)); }
 };
 
 // IEEE binary16 storage (the paper's storage precision), float arithmetic;
@@ -72,6 +75,7 @@ struct Storage<f16> {
     __device__ __forceinline__ static C cvt(R r) { return float(__builtin_bit_cast(f16, uint16_t(r))); }
     __device__ __forceinline__ static float load(const f16* p) { return float(*p); }
     __device__ __forceinline__ static void store(f16* p, float v) { *p = f16(v); }
+    __device__ __forceinline__ static C stored(C v) { return float(f16(v)); }
 };
 
 // Reciprocal for finite positive arguments: the hardware estimate refined by

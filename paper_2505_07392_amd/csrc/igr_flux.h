@@ -51,7 +51,8 @@ __device__ __forceinline__ void face_flux6(const C (&v)[6][6], int d, C gamma, C
 template <class T, int MODE, int TY, int ORDER>
 __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out, const double* __restrict__ dtp,
-    double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc) {
+    double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc,
+    double* __restrict__ speed) {
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int TX = FLUX_TX;
@@ -92,6 +93,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     C q[6][6];
     C Fz_prev[5];
     bool bad = false;
+    // fused CFL maximum of the last stage (FP32 arithmetic only: the FP64
+    // kernel is at its register limit): one LDS slot per thread, since a
+    // register carried through the plane loop would raise its peak
+    constexpr bool FUSE = MODE == MODE_STAGE3 && sizeof(C) == 4;
+    __shared__ double smax[FUSE ? FLUX_TX * (TY + 1) : 1];
+    if (FUSE) smax[tid] = 0.0;
     // columns that are never loaded keep a valid state (their faces are
     // evaluated but discarded)
 #pragma unroll
@@ -305,6 +312,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             // C: divergence and stage update
             if (col_out) {
                 const long long o = col + (long long)(k + G) * sz;
+                double vs[5];
                 C L[5];
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
@@ -328,7 +336,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                         v = unv[f] * (C(1) / C(3)) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
                     }
                     S::store(out + of, v);
+                    if (FUSE) vs[f] = double(S::stored(v));
                 }
+                // last stage: CFL speed of the new state as stored (for the
+                // next step's dt), when the caller asked for it
+                if (FUSE && speed != nullptr)
+                    smax[tid] = fmax(smax[tid], cfl_speed(g, vs[0], vs[1], vs[2], vs[3], vs[4], bad));
             }
         }
         if (col_out) {
@@ -337,6 +350,19 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         }
         // the next iteration overwrites pl only after every wave passed the
         // second barrier above, and fx/fy only after its first barrier
+    }
+    if (FUSE && speed != nullptr) {
+        // block maximum: each wave's slots by shuffles, then the waves
+        double m = smax[tid];
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        __syncthreads();
+        if (lane == 0) smax[wv] = m;
+        __syncthreads();
+        if (tid == 0) {
+            double mm = 0.0;
+            for (int w = 0; w <= TY; ++w) mm = fmax(mm, smax[w]);
+            speed[blockIdx.x] = mm;
+        }
     }
     if (bad) flag[0] = 1;
 }

@@ -20,21 +20,47 @@ enum FluxMode { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3 
 // Boundary ghosts
 // ---------------------------------------------------------------------------
 
-// One thread per (transverse cell, side) of the faces normal to `axis`;
-// writes the three ghost layers of the five fields.  Only face ghosts are
-// written (edges and corners are never read by the axis-aligned stencils).
+// Face ghosts depend on interior cells only, so the faces of all three axes
+// are filled by one launch: thread t is mapped to (axis, side, transverse
+// cell), z faces first (their rows are contiguous), then y, then x.
+// Returns false for threads past the last face.
+__device__ __forceinline__ bool bc_face_of(const Geom& g, long long t, int& axis, long long& r) {
+    const long long nz2 = 2LL * g.n[0] * g.n[1], ny2 = 2LL * g.n[0] * g.n[2], nx2 = 2LL * g.n[1] * g.n[2];
+    if (t < nz2) {
+        axis = 2;
+        r = t;
+    } else if (t < nz2 + ny2) {
+        axis = 1;
+        r = t - nz2;
+    } else if (t < nz2 + ny2 + nx2) {
+        axis = 0;
+        r = t - nz2 - ny2;
+    } else {
+        return false;
+    }
+    return true;
+}
+
+inline long long bc_face_threads(const Geom& g) {
+    return 2LL * g.n[0] * g.n[1] + 2LL * g.n[0] * g.n[2] + 2LL * g.n[1] * g.n[2];
+}
+
+// One thread per (transverse cell, side) of a face: writes the three ghost
+// layers of the five fields.  Only face ghosts are written (edges and
+// corners are never read by the axis-aligned stencils).
 template <class T>
-__global__ void k_bc_state(T* __restrict__ U, Geom g, int axis, const int* __restrict__ owner,
-                           const double* __restrict__ chi, const double* __restrict__ jet) {
+__global__ void k_bc_state(T* __restrict__ U, Geom g, const int* __restrict__ owner, const double* __restrict__ chi,
+                           const double* __restrict__ jet) {
     using S = Storage<T>;
     using C = typename S::C;
+    int axis;
+    long long r;
+    if (!bc_face_of(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, axis, r)) return;
     const int a = axis == 0 ? 1 : 0;
     const int b = axis == 2 ? 1 : 2;
     const long long tot = (long long)g.n[a] * g.n[b];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * tot) return;
-    const int side = t >= tot;
-    const long long r = t - side * tot;
+    const int side = r >= tot;
+    r -= side * tot;
     const int ia = int(r % g.n[a]);
     const int ib = int(r / g.n[a]);
     const long long base = (long long)(ia + G) * g.st[a] + (long long)(ib + G) * g.st[b];
@@ -62,14 +88,15 @@ __global__ void k_bc_state(T* __restrict__ U, Geom g, int axis, const int* __res
 }
 
 template <class T>
-__global__ void k_bc_sigma(T* __restrict__ Sg, Geom g, int axis) {
+__global__ void k_bc_sigma(T* __restrict__ Sg, Geom g) {
+    int axis;
+    long long r;
+    if (!bc_face_of(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, axis, r)) return;
     const int a = axis == 0 ? 1 : 0;
     const int b = axis == 2 ? 1 : 2;
     const long long tot = (long long)g.n[a] * g.n[b];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * tot) return;
-    const int side = t >= tot;
-    const long long r = t - side * tot;
+    const int side = r >= tot;
+    r -= side * tot;
     const int ia = int(r % g.n[a]);
     const int ib = int(r / g.n[a]);
     T* F = Sg + (long long)(ia + G) * g.st[a] + (long long)(ib + G) * g.st[b];
@@ -244,6 +271,18 @@ struct SumOp {
     __device__ double operator()(double a, double b) const { return a + b; }
 };
 
+// CFL speed of one cell, sum_d (|u_d| + c)/h_d, in FP64 whatever the
+// storage (the time-step rule of reading R10); flags rho <= 0 or p <= 0.
+// Shared by the standalone reduction and the one fused into the last RK
+// stage, so both give the same maximum.
+__device__ __forceinline__ double cfl_speed(const Geom& g, double rho, double mx, double my, double mz, double E,
+                                            bool& bad) {
+    const double p = (g.gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) / rho);
+    bad |= !(rho > 0.0) | !(p > 0.0);
+    const double c = sqrt(g.gamma * p / rho);
+    return (fabs(mx / rho) + c) * g.ih[0] + (fabs(my / rho) + c) * g.ih[1] + (fabs(mz / rho) + c) * g.ih[2];
+}
+
 // max over cells of sum_d (|u_d| + c)/h_d, in FP64 whatever the storage.
 template <class T>
 __global__ void k_speed_partial(const T* __restrict__ U, Geom g, double* __restrict__ partial,
@@ -259,16 +298,9 @@ __global__ void k_speed_partial(const T* __restrict__ U, Geom g, double* __restr
         const int j = int(r % g.n[1]);
         const int k = int(r / g.n[1]);
         const long long o = cell_offset(g, i, j, k);
-        const double rho = double(S::load(U + o));
-        const double mx = double(S::load(U + g.fs + o));
-        const double my = double(S::load(U + 2 * g.fs + o));
-        const double mz = double(S::load(U + 3 * g.fs + o));
-        const double E = double(S::load(U + 4 * g.fs + o));
-        const double p = (g.gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) / rho);
-        bad |= !(rho > 0.0) | !(p > 0.0);
-        const double c = sqrt(g.gamma * p / rho);
-        const double s = (fabs(mx / rho) + c) * g.ih[0] + (fabs(my / rho) + c) * g.ih[1] +
-                         (fabs(mz / rho) + c) * g.ih[2];
+        const double s = cfl_speed(g, double(S::load(U + o)), double(S::load(U + g.fs + o)),
+                                   double(S::load(U + 2 * g.fs + o)), double(S::load(U + 3 * g.fs + o)),
+                                   double(S::load(U + 4 * g.fs + o)), bad);
         m[0] = fmax(m[0], s);
     }
     if (bad) flag[0] = 1;

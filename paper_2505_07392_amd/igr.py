@@ -67,6 +67,8 @@ _SIGNATURES = {
     "igr_rhs": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "igr_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_rhs_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_step_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -216,6 +218,18 @@ class Solver:
         dt = ctypes.c_double(0.0)
         _check(lib().igr_step(self._ctx, _ptr(U), _ptr(sigma), cfl, dt_fixed,
                               ctypes.byref(dt) if sync else None, self._stream()))
+        return dt.value if sync else None
+
+    def advance(self, U: torch.Tensor, sigma: torch.Tensor, nsteps: int, cfl: float = 0.5, dt_fixed: float = 0.0,
+                sync: bool = True) -> Optional[float]:
+        """nsteps SSP-RK3 steps in place (each later step's CFL maximum is
+        fused into the previous step's last stage); returns the last dt
+        (and checks the non-finite flag) when sync is True."""
+        self._validate(U, 5, "U")
+        self._validate(sigma, 1, "sigma")
+        dt = ctypes.c_double(0.0)
+        _check(lib().igr_advance(self._ctx, _ptr(U), _ptr(sigma), int(nsteps), cfl, dt_fixed,
+                                 ctypes.byref(dt) if sync else None, self._stream()))
         return dt.value if sync else None
 
     def rhs_adjoint(self, U, sigma_prev, rhs_bar, sigma_bar):

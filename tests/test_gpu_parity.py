@@ -225,6 +225,29 @@ def test_step_cfl(case):
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
 
 
+@pytest.mark.parametrize("precision", ["f64", "f16"])
+def test_advance_equals_repeated_steps(case, precision):
+    """igr_advance (CFL maxima fused into each step's last stage) gives the
+    states and time steps of the same number of igr_step calls."""
+    name, w = case
+    w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 14, amp=0.1, umax=0.3))
+    banner(f"advance x4 vs step x4 {name} {precision}")
+    s = igr.Solver.from_workload(w, precision=precision)
+    U1, U2 = s.state_from(w.U), s.state_from(w.U)
+    S1, S2 = s.field_from(_sigma0(w)), s.field_from(_sigma0(w))
+    dts = [s.step(U1, S1, cfl=0.5) for _ in range(4)]
+    dt_last = s.advance(U2, S2, 4, cfl=0.5)
+    # the two maxima are the same FP64 expression on the same stored values;
+    # allow one rounding of dt in case the compiler contracts it differently
+    assert abs(dt_last - dts[-1]) <= 1e-15 * dts[-1]
+    tol = 1e-14 if precision == "f64" else 2e-3     # a few units of the 16-bit storage
+    a, b = to_host(s, U1).astype(np.float64), to_host(s, U2).astype(np.float64)
+    d = rel_linf(b, a).max()
+    print(f"  max rel diff advance vs steps: {d:.3e}", flush=True)
+    assert d <= tol
+    assert rel_linf(to_host(s, S2).astype(np.float64), to_host(s, S1).astype(np.float64)).max() <= tol
+
+
 def test_dt_and_sums(case):
     name, w = case
     banner(f"dt/sums {name}")
