@@ -224,8 +224,10 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
-            if constexpr (sizeof(C) != 4) {
-                // FP64: faces one after the other (register budget)
+            {
+                // faces one direction at a time (the register budget sets
+                // the tile height, and more waves beat more independent
+                // chains per wave)
                 // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv;
                 // wave TY, lanes < TY: face x0-1/2 of row `lane`.  One code path.
                 {
@@ -263,43 +265,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                 }
             }
         }
-        // B3: z face k+1/2 from the queue (also at k = z0-1 to prime Fz_prev).
-        // FP32 arithmetic: the x, y and z faces are evaluated together in one
-        // basic block every iteration (predicated stores), so their
-        // independent dependency chains interleave; every face of a direction
-        // still runs through the same instructions.
+        // B3: z face k+1/2 from the queue (also at k = z0-1 to prime Fz_prev)
         C Fz[5];
-        if constexpr (sizeof(C) == 4) {
-            const int r = own ? wv : (lane < TY ? lane : 0);
-            const int fi = own ? lane + 1 : 0;
-            const int gxf = x0 + fi - 1;
-            const bool actx = body && (own || lane < TY) && (y0 + r) < ny && gxf >= -1 && gxf < nx;
-            const int gyf = y0 + wv;
-            const bool acty = body && (x0 + lane) < nx && gyf >= 0 && gyf <= ny;
-            C vx[6][6], vy[6][6], vz[6][6];
-#pragma unroll
-            for (int f = 0; f < 6; ++f)
-#pragma unroll
-                for (int p = 0; p < 6; ++p) {
-                    vx[f][p] = pl[f][r + G][fi + p];
-                    vy[f][p] = pl[f][wv + p][lane + G];
-                    vz[f][p] = q[f][p];
-                }
-            C Fx[5], Fy[5];
-            bool bx = false, by = false, bz = false;
-            face_flux6<C, ORDER>(vx, 0, gamma, Fx, bx);
-            face_flux6<C, ORDER>(vy, 1, gamma, Fy, by);
-            face_flux6<C, ORDER>(vz, 2, gamma, Fz, bz);
-            if (actx) {
-#pragma unroll
-                for (int f = 0; f < 5; ++f) fx[f][r][fi] = Fx[f];
-            }
-            if (acty) {
-#pragma unroll
-                for (int f = 0; f < 5; ++f) fy[f][wv][lane] = Fy[f];
-            }
-            bad |= (actx && bx) || (acty && by) || (col_out && bz);
-        } else if (col_out) {
+        if (col_out) {
             C v[6][6];
 #pragma unroll
             for (int f = 0; f < 6; ++f)
