@@ -222,11 +222,11 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 #ifndef IGR_PAIR_ZC_MIN
 #define IGR_PAIR_ZC_MIN 8
 #endif
-template <class T>
+template <class T, bool FIRST>
 int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
     using C = typename Storage<T>::C;
     const Geom& g = c->g;
-    constexpr int NR = PAIR_NR;
+    constexpr int NR = FIRST ? PAIR_NR_FIRST : PAIR_NR;
     const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + NR - 3) / (NR - 2);
     const long long tiles = (long long)tiles_x * tiles_y;
     long long zc = (tiles * g.n[2] + IGR_PAIR_BLOCKS - 1) / IGR_PAIR_BLOCKS;
@@ -235,18 +235,19 @@ int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
     if (zc > g.n[2]) zc = g.n[2];
     const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
     if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
-    const C* b = static_cast<const C*>(c->d_b);
-    const C* ir = static_cast<const C*>(c->d_ir);
+    C* b = static_cast<C*>(c->d_b);
+    C* ir = static_cast<C*>(c->d_ir);
     return launch(c, K_JACOBI, s, [&] {
-        k_sweep_pair<T, NR><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(U, Sin, Sout, b, ir, g, int(zc),
-                                                                               tiles_x, tiles_y);
+        k_sweep_pair<T, NR, FIRST><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(U, Sin, Sout, b, ir, g,
+                                                                                      int(zc), tiles_x, tiles_y);
     });
 }
 
 // nsweeps Jacobi sweeps from `sig` (warm start); U ghosts must be filled.
 // sigma_block 1: one z-marching sweep per pass, the source (and, in FP64,
-// 1/rho) formed in the first pass and stored; 2: the same first pass, then
-// two sweeps per pass; 3..5: passes of up to that many levels of the
+// 1/rho) formed in the first pass and stored; 2: two sweeps per pass (for
+// an even count the first pass also forms the source, else a single first
+// sweep does); 3..5: passes of up to that many levels of the
 // temporally blocked kernel that forms the source itself.  The last
 // iterate ends in `sig` (device copy after an odd number of passes) and
 // its ghosts are filled.
@@ -312,14 +313,25 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             return fill_sigma_ghosts(c, src, s);
         }
         int left = nsweeps;
-        if (left > 0) {
+#ifndef IGR_FIRST_PAIR
+#define IGR_FIRST_PAIR 1
+#endif
+        if (IGR_FIRST_PAIR && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
+            // an even count: the first two sweeps in one pass that also
+            // forms the source, then pairs (an odd count keeps the single
+            // first sweep, then pairs: measured faster than first pass +
+            // pairs + a single sweep)
+            IGR_TRY((pair_pass<T, true>(c, U, src, dst, s)));
+            swap();
+            left -= 2;
+        } else if (left > 0) {
             IGR_TRY(single(true));
             swap();
             --left;
         }
         if (c->sigma_block == 2) {
             for (; left >= 2; left -= 2) {
-                IGR_TRY(pair_pass<T>(c, U, src, dst, s));
+                IGR_TRY((pair_pass<T, false>(c, U, src, dst, s)));
                 swap();
             }
         }

@@ -526,30 +526,49 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
 #endif
 constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
 
+#ifndef IGR_PAIR_NR_FIRST
+#define IGR_PAIR_NR_FIRST 7
+#endif
+constexpr int PAIR_NR_FIRST = IGR_PAIR_NR_FIRST;   // rows per block of the first pass of a solve
+
+template <class T, bool FIRST>
+struct PairIn;
 template <class T>
-struct PairIn {     // loads of one plane for one thread (register form R)
+struct PairIn<T, false> {   // loads of one plane for one thread (register form R)
     using C = typename Storage<T>::C;
     using R = typename Storage<T>::R;
     R s0, ir;       // own column: Sigma, rho (or 1/rho when stored)
     C b;            // own column: b
     R xs0, xir;     // the ring-2 row (rows 0 and NR-1; others: own column)
 };
+template <class T>
+struct PairIn<T, true> {    // first pass of a solve: the state instead of b and 1/rho
+    using R = typename Storage<T>::R;
+    R s0, rho, m[3];
+    R xs0, xrho, xm[3];
+};
 
-template <class T, int NR>
+// FIRST: the first pass of a solve, which also forms the source b (eq. 9's
+// left side, second-order central velocity gradients) at every level-1
+// cell from u = m/rho in LDS (x/y neighbours) and a register queue (z), and
+// stores b and, in FP64, 1/rho for the later passes -- the work of the
+// single first sweep fused into the pair.
+template <class T, int NR, bool FIRST>
 __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restrict__ U, const T* __restrict__ Sin,
                                                             T* __restrict__ Sout,
-                                                            const typename Storage<T>::C* __restrict__ b,
-                                                            const typename Storage<T>::C* __restrict__ irs, Geom g,
+                                                            typename Storage<T>::C* __restrict__ b,
+                                                            typename Storage<T>::C* __restrict__ irs, Geom g,
                                                             int zc, int tiles_x, int tiles_y) {
     using S = Storage<T>;
     using C = typename S::C;
-    constexpr bool IRS = sizeof(C) == 8;   // 1/rho stored by the first sweep (FP64)
+    constexpr bool IRS = sizeof(C) == 8;   // 1/rho stored by the first pass (FP64)
     constexpr int PD = 2;                   // planes loaded ahead (= register slots)
     constexpr int W0 = 68;                  // input row: columns x0-2 .. x0+65
     constexpr int W1 = 66;                  // level-1 and b row: x0-1 .. x0+64
     __shared__ C ls0[4][NR + 2][W0];
     __shared__ C lir[4][NR + 2][W0];
-    __shared__ C lb[3][NR][W1];
+    __shared__ C lb[FIRST ? 1 : 3][FIRST ? 1 : NR][FIRST ? 1 : W1];
+    __shared__ C lu[FIRST ? 3 : 1][FIRST ? 3 : 1][FIRST ? NR + 2 : 1][FIRST ? W0 : 1];
     __shared__ C ls1[2][NR][W1];
     static_assert(4 * NR - 4 <= 64, "side columns must fit one wave");
 
@@ -562,6 +581,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     const int x0 = bx * 64, y0 = by * (NR - 2), z0 = bz * zc;
     const int z1 = min(z0 + zc, nz);
     const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+    const long long fs = g.fs;
 
     // role of this thread: its column (lx, ly) in tile coordinates
     int lx = threadIdx.x, ly = threadIdx.y;
@@ -596,29 +616,39 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
         return c < lo ? lo : (c > hi ? hi : c);
     };
     const int sy = g.st[1], sz = g.st[2];
-    // Sigma and b: interior cells; 1/rho: the first ghost layer is valid too
+    // Sigma and b: interior cells; rho, m and 1/rho: the first ghost layer is valid too
     const long long csig = (long long)(src(gy, ny, py, 0, ny - 1) + G) * sy + (src(gx, nx, px, 0, nx - 1) + G);
     const long long cir = (long long)(src(gy, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
     const long long xsig = (long long)(src(gyx, ny, py, 0, ny - 1) + G) * sy + (src(gx, nx, px, 0, nx - 1) + G);
     const long long xir = (long long)(src(gyx, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
-    // every lane issues the same five loads at clamped planes
-    auto load = [&](int P, PairIn<T>& q) {
+    // every lane issues the same loads at clamped planes
+    auto load = [&](int P, PairIn<T, FIRST>& q) {
         const long long os = (long long)(src(P, nz, pz, 0, nz - 1) + G) * sz;
         const long long oi = (long long)(src(P, nz, pz, -1, nz) + G) * sz;
         q.s0 = S::load_raw(Sin + os + csig);
-        q.b = b[os + csig];
         q.xs0 = S::load_raw(Sin + os + xsig);
-        if constexpr (IRS) {
-            q.ir = irs[oi + cir];
-            q.xir = irs[oi + xir];
+        if constexpr (FIRST) {
+            q.rho = S::load_raw(U + oi + cir);
+            q.xrho = S::load_raw(U + oi + xir);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                q.m[c] = S::load_raw(U + (1 + c) * fs + oi + cir);
+                q.xm[c] = S::load_raw(U + (1 + c) * fs + oi + xir);
+            }
         } else {
-            q.ir = S::load_raw(U + oi + cir);
-            q.xir = S::load_raw(U + oi + xir);
+            q.b = b[os + csig];
+            if constexpr (IRS) {
+                q.ir = irs[oi + cir];
+                q.xir = irs[oi + xir];
+            } else {
+                q.ir = S::load_raw(U + oi + cir);
+                q.xir = S::load_raw(U + oi + xir);
+            }
         }
     };
     using R = typename S::R;
     auto inv = [](R v) {
-        if constexpr (IRS)
+        if constexpr (IRS && !FIRST)
             return v;
         else
             return fast_rcp(S::cvt(v));
@@ -637,18 +667,45 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     // last (level 2 updates that cell one iteration later)
     JacCoef<C> kc = {C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
     C bprev = C(0);
+    C uq[3][3] = {};                          // FIRST: u of the own column at planes P-2, P-1, P
 
-    auto iter = [&](int P, PairIn<T>& slot) {
+    auto iter = [&](int P, PairIn<T, FIRST>& slot) {
         // publish plane P, then refill the slot with plane P+PD
         const int w4 = (P + 8) % 4, w3 = (P + 6) % 3;
-        if (act) {
-            ls0[w4][cy][cx] = S::cvt(slot.s0);
-            lir[w4][cy][cx] = inv(slot.ir);
-        }
-        if (hasb) lb[w3][ly][bxc] = slot.b;
-        if (xrow) {
-            ls0[w4][xr][cx] = S::cvt(slot.xs0);
-            lir[w4][xr][cx] = inv(slot.xir);
+        if constexpr (FIRST) {
+            const C ir = inv(slot.rho);
+            C u[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u[c] = S::cvt(slot.m[c]) * ir;
+            if (act) {
+                ls0[w4][cy][cx] = S::cvt(slot.s0);
+                lir[w4][cy][cx] = ir;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lu[c][w3][cy][cx] = u[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                uq[c][0] = uq[c][1];
+                uq[c][1] = uq[c][2];
+                uq[c][2] = u[c];
+            }
+            if (xrow) {
+                const C xi = inv(slot.xrho);
+                ls0[w4][xr][cx] = S::cvt(slot.xs0);
+                lir[w4][xr][cx] = xi;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lu[c][w3][xr][cx] = S::cvt(slot.xm[c]) * xi;
+            }
+        } else {
+            if (act) {
+                ls0[w4][cy][cx] = S::cvt(slot.s0);
+                lir[w4][cy][cx] = inv(slot.ir);
+            }
+            if (hasb) lb[w3][ly][bxc] = slot.b;
+            if (xrow) {
+                ls0[w4][xr][cx] = S::cvt(slot.xs0);
+                lir[w4][xr][cx] = inv(slot.xir);
+            }
         }
         load(min(P + PD, z1 + 1), slot);
         __syncthreads();
@@ -668,7 +725,41 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
                               ylo ? sc : ls0[a4][cy - 1][cx], yhi ? sc : ls0[a4][cy + 1][cx],
                               (!pz && z == 0) ? sc : ls0[m4][cy][cx], (!pz && z == nz - 1) ? sc : ls0[w4][cy][cx]};
             kn = jacobi_coef(lir[a4][cy][cx], irv, alpha, hx2, hy2, hz2);
-            bn = lb[(P + 5) % 3][ly][bxc];
+            if constexpr (FIRST) {
+                // source at this cell, eq. (9) left side
+                const int a3 = (P + 5) % 3;
+                C Gm[3][3];
+                const C scx = C(0.5) * C(g.ih[0]), scy = C(0.5) * C(g.ih[1]), scz = C(0.5) * C(g.ih[2]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Gm[c][0] = (lu[c][a3][cy][cx + 1] - lu[c][a3][cy][cx - 1]) * scx;
+                    Gm[c][1] = (lu[c][a3][cy + 1][cx] - lu[c][a3][cy - 1][cx]) * scy;
+                    Gm[c][2] = (uq[c][2] - uq[c][0]) * scz;
+                }
+                const C tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
+                C tr2 = C(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
+                bn = alpha * (tr2 + tr * tr);
+                if (outp && z >= z0 && z < z1) {
+                    // b and (FP64) 1/rho, face-ghost layer included, for the later passes
+                    const long long o = (long long)(z + G) * sz + (long long)(gy + G) * sy + (gx + G);
+                    b[o] = bn;
+                    if constexpr (IRS) {
+                        irs[o] = lir[a4][cy][cx];
+                        if (gx == 0) irs[o - 1] = lir[a4][cy][cx - 1];
+                        if (gx == nx - 1) irs[o + 1] = lir[a4][cy][cx + 1];
+                        if (gy == 0) irs[o - sy] = lir[a4][cy - 1][cx];
+                        if (gy == ny - 1) irs[o + sy] = lir[a4][cy + 1][cx];
+                        if (z == 0) irs[o - sz] = lir[m4][cy][cx];
+                        if (z == nz - 1) irs[o + sz] = lir[w4][cy][cx];
+                    }
+                }
+            } else {
+                bn = lb[(P + 5) % 3][ly][bxc];
+            }
             v1 = jacobi_apply(bn, kn, sgv, alpha, hx2, hy2, hz2);
             ls1[(P + 7) & 1][ly][bxc] = v1;
         }
@@ -690,7 +781,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
         qs1[1] = v1;
     };
 
-    PairIn<T> pa, pb;
+    PairIn<T, FIRST> pa, pb;
     load(z0 - 2, pa);
     load(z0 - 1, pb);
     int P = z0 - 2;
