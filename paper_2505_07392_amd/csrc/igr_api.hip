@@ -421,17 +421,17 @@ FluxLaunch flux_launch(const Geom& g, int ty, int target_blocks) {
 
 template <class T, int MODE>
 int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
-              hipStream_t s, double* speed = nullptr) {
+              hipStream_t s, double* speed = nullptr, T* sig_out = nullptr) {
     constexpr int TY = FluxShape<T>::TY;
     const FluxLaunch L = flux_launch(c->g, TY, FluxShape<T>::BLOCKS);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
         if (c->order == 3)
             k_flux_tiled<T, MODE, TY, 3><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed);
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
         else
             k_flux_tiled<T, MODE, TY, 5><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed);
+                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
     });
 }
 
@@ -497,11 +497,12 @@ int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hi
     IGR_TRY(fill_state_ghosts(c, Ua, s));
     IGR_TRY(solve(Ua));
     IGR_TRY((flux_impl<T, MODE_STAGE2>(c, Ua, cur, U, Ub, dtp, dt_fixed, s)));
-    // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un
+    // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
+    // solve ended in the scratch copy the kernel also writes Sigma's interior
+    // into the caller's buffer (its ghosts are scratch)
     IGR_TRY(fill_state_ghosts(c, Ub, s));
     IGR_TRY(solve(Ub));
-    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s, speed)));
-    if (cur != sig) IGR_HIP(hipMemcpyAsync(sig, cur, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
+    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s, speed, cur != sig ? sig : nullptr)));
     return IGR_OK;
 }
 

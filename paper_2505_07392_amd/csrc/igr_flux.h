@@ -52,7 +52,7 @@ template <class T, int MODE, int TY, int ORDER>
 __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out, const double* __restrict__ dtp,
     double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc,
-    double* __restrict__ speed) {
+    double* __restrict__ speed, T* __restrict__ sig_out) {
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int TX = FLUX_TX;
@@ -306,6 +306,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     S::store(out + of, v);
                     if (FUSE) vs[f] = double(S::stored(v));
                 }
+                // last stage: the solved Sigma of this plane into the caller's
+                // buffer when the solve ended in the scratch copy
+                if (MODE == MODE_STAGE3 && sig_out != nullptr) S::store(sig_out + o, q[5][2]);
                 // last stage: CFL speed of the new state as stored (for the
                 // next step's dt), when the caller asked for it
                 if (FUSE && speed != nullptr)
