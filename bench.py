@@ -29,35 +29,38 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2505_07392_amd", "csrc")
 
 
-def sigma_schedule(nsweeps: int, precision: str, sigma_block: int = 0, smoother: str = "jacobi"):
-    """Launches of one Sigma solve as the library runs them: (first sweep,
-    two-sweep passes, later single sweeps).  The default (0) is two-sweep
-    passes in FP64 and single sweeps in the forms with FP32 arithmetic.
+def sigma_schedule(nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
+    """Launches of one Sigma solve as the library runs them for the pass
+    structure a context reports (Solver.sigma_block, default resolved):
+    (passes that form the source, later two-sweep passes, later single
+    sweeps).  With two-sweep passes an even count starts with a two-sweep
+    pass that forms the source, an odd count with a single sweep.
     Red-black Gauss-Seidel runs two in-place half-sweeps per sweep, each
     counted here as a single sweep."""
-    if smoother == "rbgs":
-        return (1, 0, 2 * nsweeps - 1) if nsweeps else (0, 0, 0)
-    sb = sigma_block or (2 if precision == "f64" else 1)
-    if sb > 2:
-        raise ValueError("the fused-source march passes are not modelled here")
     if nsweeps == 0:
         return 0, 0, 0
+    if smoother == "rbgs":
+        return 1, 0, 2 * nsweeps - 1
+    if sigma_block not in (1, 2):
+        raise ValueError("the fused-source march passes are not modelled here")
+    if sigma_block == 2 and nsweeps % 2 == 0:
+        return 1, (nsweeps - 2) // 2, 0
     later = nsweeps - 1
-    pairs = later // 2 if sb == 2 else 0
+    pairs = later // 2 if sigma_block == 2 else 0
     return 1, pairs, later - 2 * pairs
 
 
-def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int, precision: str = "f64",
-                               sigma_block: int = 0, smoother: str = "jacobi") -> float:
+def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int, sigma_block: int = 2,
+                               smoother: str = "jacobi") -> float:
     """Compulsory HBM bytes per interior cell for one launch of `kernel`
     (averaged over the launches of one right-hand side)."""
     if kernel == "flux_rk":
         # stage 1 reads U (5) + Sigma (1), writes 5; stages 2 and 3 also read Un (5)
         return esize * (11 + 16 + 16) / 3.0
     if kernel == "jacobi":
-        # first sweep: reads rho, m, Sigma; writes Sigma, b.  Later sweeps,
-        # single or two per pass: read Sigma, rho, b; write Sigma
-        nf, npair, nsingle = sigma_schedule(nsweeps, precision, sigma_block, smoother)
+        # first pass (one or two sweeps): reads rho, m, Sigma; writes Sigma,
+        # b.  Later passes, single or two sweeps: read Sigma, rho, b; write Sigma
+        nf, npair, nsingle = sigma_schedule(nsweeps, sigma_block, smoother)
         first = 5 * esize + esize + csize
         later = 3 * esize + csize
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
@@ -68,16 +71,17 @@ def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int
     raise KeyError(kernel)
 
 
-def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int = 0, smoother: str = "jacobi"):
+def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
     """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
-    Sigma kernels from their measured average launch time."""
+    Sigma kernels from their measured average launch time (sigma_block: the
+    pass structure the context ran)."""
     esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
     csz = 8 if precision == "f64" else 4
     out = {}
     for k in ("flux_rk", "jacobi"):
         ms, cnt = kt[k]
         if cnt:
-            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, precision, sigma_block, smoother) * cells
+            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, sigma_block, smoother) * cells
             gbs = ab / (ms / cnt / 1e3) / 1e9
             out[k] = {"avg_ms": round(ms / cnt, 5), "launches": cnt, "achieved_GBs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -149,8 +153,9 @@ def run_form(w, precision, steps, warmup, sigma_block=0, order=5, smoother="jaco
     s.timing(False)
     s.check()
     kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
+    sb = s.sigma_block
     s.close()
-    return el, kt
+    return el, kt, sb
 
 
 def jet_workload(n: int, nsteps: int):
@@ -200,7 +205,8 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
         kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
         form = {"value": w.cells * timed_steps / el, "ms_per_step": 1e3 * el / timed_steps,
                 "device_bytes_in_use": total - free, "frac_of_288GB": (total - free) / 288e9}
-        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps))
+        form["sigma_block"] = s.sigma_block
+        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block))
         if nsteps > 0:
             print(f"[bench] multi-jet {n}^3 {prec}: {nsteps}-step run", file=sys.stderr, flush=True)
             U.copy_(U0)
@@ -285,7 +291,7 @@ def main():
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
     csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 
-    el, kt = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
+    el, kt, sb = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
     value = cells * args.steps / el
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -293,7 +299,7 @@ def main():
     avg_s = ms / count / 1e3
     try:
         abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps,
-                                            args.precision, args.sigma_block, args.smoother) * cells
+                                            sb, args.smoother) * cells
     except KeyError:
         abytes = None
     workload = f"periodic_box_{args.n}"
@@ -310,16 +316,16 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x and x != args.precision]:
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, kt2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
+        e2, kt2, sb2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
         forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
-                    "vs_f64": None}
-        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, args.sigma_block, args.smoother))
+                    "vs_f64": None, "sigma_block": sb2}
+        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, sb2, args.smoother))
 
     if args.precision == "f64":
         for f in forms:
             forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
     kernels.update({k + "_roofline": v for k, v in kernel_rooflines(kt, cells, args.precision, w.nsweeps,
-                                                                    args.sigma_block, args.smoother).items()})
+                                                                    sb, args.smoother).items()})
     line = {
         "metric": "cell-updates/s per RK3 step (incl. Sigma Jacobi)",
         "value": value,
@@ -337,7 +343,7 @@ def main():
         "config": {"workload": f"{workload} periodic box {args.n}^3, rms Mach 1.5, alpha=dx^2, "
                                f"{w.nsweeps} Jacobi sweeps, CFL 0.5", "cells": cells,
                    "sweeps": w.nsweeps, "precision": args.precision, "order": args.order,
-                   "smoother": args.smoother},
+                   "smoother": args.smoother, "sigma_block": sb},
         "roofline": roofline,
         "kernels": kernels,
         "forms": forms,

@@ -122,8 +122,10 @@ typedef struct {
  * pass (the first also forms the source); 2 runs that first pass and then
  * two sweeps per pass (temporally blocked, reusing the stored source);
  * 3..5 run passes of up to that many sweeps of a kernel that forms the
- * source itself.  0 selects the default: 2 for IGR_F64, 1 for the forms
- * with FP32 arithmetic.  Results agree to rounding.  smoother selects the
+ * source itself.  0 selects the default: 2 for IGR_F64; for the forms
+ * with FP32 arithmetic, 1 while one sweep's working set (padded field
+ * elements x (3 x storage bytes + 4)) fits the 256 MiB last-level cache,
+ * else 2 (igr_get_opts reports the choice).  Results agree to rounding.  smoother selects the
  * sweep: IGR_SMOOTH_JACOBI (default), or IGR_SMOOTH_RBGS, red-black
  * Gauss-Seidel (the paper's alternative, "Discretization"): each sweep
  * updates the cells with i + j + k even, then the others, in place, each
@@ -154,6 +156,10 @@ const char *igr_last_error(void);
 
 /* Elements per padded field, (nz+6)*(ny+6)*(nx+6), and bytes per element. */
 int igr_field_size(const igr_ctx *ctx, int64_t *elems, int32_t *elem_bytes);
+
+/* The options a context runs with, defaults resolved (sigma_block is never
+ * 0 here). */
+int igr_get_opts(const igr_ctx *ctx, igr_opts *out);
 
 /* Replace the primitive state (rho, ux, uy, uz, p) of inflow disc `index`
  * (geometry unchanged).  Takes effect for later calls. */

@@ -216,6 +216,11 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 
 // Launch of the two-sweep pass: 64 x (PAIR_NR-2) output tiles, z chunks
 // sized for about IGR_PAIR_BLOCKS blocks of 64 x (PAIR_NR+1) threads.
+// Last-level (Infinity) cache of one MI355X, bytes.
+#ifndef IGR_LLC_BYTES
+#define IGR_LLC_BYTES (256.0 * 1024 * 1024)
+#endif
+
 #ifndef IGR_PAIR_BLOCKS
 #define IGR_PAIR_BLOCKS 2048
 #endif
@@ -889,10 +894,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->nsweeps = opts->nsweeps;
     c->order = opts->order;
     c->smoother = opts->smoother;
-    // default: two sweeps per pass where the arithmetic is FP64 (the
-    // sweeps are then bound by memory), single sweeps otherwise (FP32
-    // arithmetic on 2- or 4-byte storage: the single-sweep kernel is faster)
-    c->sigma_block = opts->sigma_block != 0 ? opts->sigma_block : (opts->precision == IGR_F64 ? 2 : 1);
+    c->sigma_block = opts->sigma_block;   // 0: resolved below, once the field size is known
     for (int f = 0; f < 6; ++f) c->faces[f] = bc->face[f];
     c->patches.assign(bc->patch, bc->patch + bc->npatch);
     const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;
@@ -916,6 +918,16 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     for (int d = 0; d < 3; ++d) g.periodic[d] = bc->face[2 * d] == IGR_BC_PERIODIC;
     c->esize = c->precision == IGR_F64 ? 8 : c->precision == IGR_F32 ? 4 : 2;   // BF16 and F16: 2
     c->csize = c->precision == IGR_F64 ? 8 : 4;
+    if (c->sigma_block == 0) {
+        // Two sweeps per pass halve the sweeps' memory traffic but cost
+        // more instructions per sweep.  In FP64 the sweeps are bound by
+        // memory at every size.  With FP32 arithmetic the single-sweep
+        // kernel wins while one sweep's working set (Sigma in and out, rho,
+        // the FP32 source) stays in the last-level cache, whose reuse the
+        // two-sweep pass cannot improve on.
+        const double sweep_bytes = double(g.fs) * (3.0 * c->esize + c->csize);
+        c->sigma_block = (c->precision == IGR_F64 || sweep_bytes > IGR_LLC_BYTES) ? 2 : 1;
+    }
 
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
@@ -973,6 +985,16 @@ int igr_field_size(const igr_ctx* ctx, int64_t* elems, int32_t* elem_bytes) {
     if (!ctx) return fail(IGR_EINVAL, "null context");
     if (elems) *elems = ctx->g.fs;
     if (elem_bytes) *elem_bytes = int32_t(ctx->esize);
+    return IGR_OK;
+}
+
+int igr_get_opts(const igr_ctx* ctx, igr_opts* out) {
+    if (!ctx || !out) return fail(IGR_EINVAL, "null argument");
+    out->precision = ctx->precision;
+    out->order = ctx->order;
+    out->nsweeps = ctx->nsweeps;
+    out->sigma_block = ctx->sigma_block;
+    out->smoother = ctx->smoother;
     return IGR_OK;
 }
 

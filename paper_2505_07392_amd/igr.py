@@ -61,6 +61,7 @@ _SIGNATURES = {
     "igr_finalize": (ctypes.c_int, [ctypes.c_void_p]),
     "igr_last_error": (ctypes.c_char_p, []),
     "igr_field_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "igr_get_opts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Opts)]),
     "igr_set_patch_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "igr_sigma_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
@@ -151,6 +152,9 @@ class Solver:
             _check(lib().igr_init(ctypes.byref(Grid(nx, ny, nz, dx, dy, dz)), gamma, alpha, ctypes.byref(bc),
                                   ctypes.byref(opts), ctypes.byref(handle)))
         self._ctx = handle
+        eff = Opts()
+        _check(lib().igr_get_opts(self._ctx, ctypes.byref(eff)))
+        self.sigma_block = eff.sigma_block   # the pass structure the library runs (default resolved)
 
     @classmethod
     def from_workload(cls, w, precision: str = "f64", nsweeps: Optional[int] = None, sigma_block: int = 0,

@@ -37,8 +37,8 @@ def rel_l1(got, want):
     return np.array(out)
 
 
-def _run_gpu(w, precision, dt, nsteps):
-    s = igr.Solver.from_workload(w, precision=precision)
+def _run_gpu(w, precision, dt, nsteps, sigma_block=0):
+    s = igr.Solver.from_workload(w, precision=precision, sigma_block=sigma_block)
     U = s.state_from(w.U)
     S = s.new_field()
     for _ in range(nsteps):
@@ -63,11 +63,12 @@ def box_reference():
     return w, dt, _run_oracle(w, dt, 20)
 
 
+@pytest.mark.parametrize("sigma_block", [1, 2])
 @pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
-def test_precision_periodic_box(box_reference, precision):
+def test_precision_periodic_box(box_reference, precision, sigma_block):
     w, dt, (Uo, So) = box_reference
-    banner(f"precision {precision}: periodic box 48^3, 20 steps")
-    Ug, Sg = _run_gpu(w, precision, dt, 20)
+    banner(f"precision {precision}: periodic box 48^3, 20 steps, sigma_block={sigma_block}")
+    Ug, Sg = _run_gpu(w, precision, dt, 20, sigma_block)
     err = rel_l1(np.concatenate([Ug, Sg[None]]), np.concatenate([Uo, So[None]]))
     print(f"[gpu-case] {precision} rel L1 (rho, mx, my, mz, E, Sigma) = {err}", flush=True)
     assert (err <= BOUND[precision]).all(), err
@@ -81,11 +82,12 @@ def jet_reference():
     return w, dt, _run_oracle(w, dt, 30)
 
 
+@pytest.mark.parametrize("sigma_block", [1, 2])
 @pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
-def test_precision_jets(jet_reference, precision):
+def test_precision_jets(jet_reference, precision, sigma_block):
     w, dt, (Uo, So) = jet_reference
-    banner(f"precision {precision}: Mach-3 jets 40^3, 30 steps")
-    Ug, Sg = _run_gpu(w, precision, dt, 30)
+    banner(f"precision {precision}: Mach-3 jets 40^3, 30 steps, sigma_block={sigma_block}")
+    Ug, Sg = _run_gpu(w, precision, dt, 30, sigma_block)
     err = rel_l1(np.concatenate([Ug, Sg[None]]), np.concatenate([Uo, So[None]]))
     keep = [i for i in range(6) if np.abs(np.concatenate([Uo, So[None]])[i]).sum() > 0]
     print(f"[gpu-case] {precision} rel L1 (rho, mx, my, mz, E, Sigma) = {err}", flush=True)
@@ -109,3 +111,22 @@ def test_fp64_parity_of_reductions_in_all_forms():
         want_s = ref.conserved_sums(prob, torch.from_numpy(Ur)).numpy()
         scale = np.abs(Ur).sum(axis=(1, 2, 3)) * w.dx ** 3
         assert (np.abs(sums - want_s) <= 1e-13 * scale).all()
+
+
+@pytest.mark.parametrize("precision,n,want", [
+    ("f64", 16, 2), ("f64", 256, 2),
+    ("f16", 256, 1), ("bf16", 256, 1), ("f16", 384, 2),
+    ("f32", 248, 1), ("f32", 256, 2),
+])
+def test_default_pass_structure(precision, n, want):
+    """sigma_block 0 resolves to two-sweep passes in FP64, and in the forms
+    with FP32 arithmetic once one sweep's working set (padded elements x
+    (3 x storage bytes + 4)) exceeds 256 MiB: 254^3 x 16 B = 250 MiB stays
+    single, 262^3 x 16 B = 274 MiB pairs.  An explicit choice is kept."""
+    banner(f"default pass structure {precision} {n}^3")
+    s = igr.Solver(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, precision=precision)
+    assert s.sigma_block == want
+    s.close()
+    s = igr.Solver(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, precision=precision, sigma_block=3 - want)
+    assert s.sigma_block == 3 - want
+    s.close()
