@@ -378,9 +378,13 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 // Launch shape of the tiled flux kernel: 64 x TY column tiles, z chunks
 // sized for >= ~2048 blocks (256 CUs, several resident blocks each).
 // Rows per tile: the block (TY+1 waves) must fill the waves one CU can
-// hold at the kernel's register use (FP64: 8 per CU, FP32: 12).
-// (measured on the 256^3 box: FP64 TY = 7 with ~2048 blocks, FP32
-// arithmetic TY = 11 with ~512 blocks; TY = 3..5 is 20-75 % slower)
+// hold at the kernel's register use (FP64: 8 per CU, FP32: 12), so one
+// block is resident per CU and a launch runs in rounds of 256 blocks.
+// Block-count targets (z chunk = tiles * nz / target, within 8..64
+// planes), measured on the 256^3 box: FP64 3072 (0.82 ms per launch;
+// 2048: 0.84, 768: 0.95), FP32 arithmetic 768, three full rounds of 32-plane
+// chunks (0.38 ms; 1024: 0.43, 2048: 0.41).  From 512^3 up the 64-plane
+// cap decides.  TY = 3..5 is 20-75 % slower.
 #ifndef IGR_FLUX_TY_F64
 #define IGR_FLUX_TY_F64 7
 #endif
@@ -388,10 +392,10 @@ int source_impl(igr_ctx* c, const T* U, hipStream_t s) {
 #define IGR_FLUX_TY_F32 11
 #endif
 #ifndef IGR_FLUX_BLOCKS_F64
-#define IGR_FLUX_BLOCKS_F64 2048
+#define IGR_FLUX_BLOCKS_F64 3072
 #endif
 #ifndef IGR_FLUX_BLOCKS_F32
-#define IGR_FLUX_BLOCKS_F32 2048
+#define IGR_FLUX_BLOCKS_F32 768
 #endif
 template <class T>
 struct FluxShape {
