@@ -3,8 +3,9 @@
 A step is one SSP-RK3 step of the whole path (three right-hand sides, each
 with its ghost fill, Sigma source, Jacobi sweeps and fused reconstruction +
 LLF flux + divergence + stage update, plus the FP64 CFL reduction; the
-timed steps run through igr_advance, which fuses each later step's CFL
-maximum into the previous step's last stage) over the
+timed steps run through igr_advance, which in the FP32-arithmetic forms
+fuses each later step's CFL maximum into the previous step's last stage)
+over the
 256^3 periodic box (rho = 1 + 0.2 * Gaussian-smoothed noise, solenoidal
 k^-2 velocity at rms Mach 1.5, p = 1, alpha = dx^2, 5 sweeps, CFL 0.5),
 with the state resident in HBM.
