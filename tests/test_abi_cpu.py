@@ -104,6 +104,9 @@ def test_null_context_calls():
     assert L.igr_rhs(None, None, None, None, None) == igr.IGR_EINVAL
     assert L.igr_step(None, None, None, 0.5, 0.0, None, None) == igr.IGR_EINVAL
     assert L.igr_check(None, None) == igr.IGR_EINVAL
+    opts = igr.Opts()
+    assert L.igr_get_opts(None, ctypes.byref(opts)) == igr.IGR_EINVAL
+    assert L.igr_advance(None, None, None, 1, 0.5, 0.0, None, None) == igr.IGR_EINVAL
 
 
 def test_kernel_names():
