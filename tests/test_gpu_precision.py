@@ -130,3 +130,44 @@ def test_default_pass_structure(precision, n, want):
     s = igr.Solver(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, precision=precision, sigma_block=3 - want)
     assert s.sigma_block == 3 - want
     s.close()
+
+
+# one-step bound per form at full size, relative to each field's maximum:
+# the three stage values are rounded to storage once each (FP32: 2^-24,
+# FP16: 2^-11, BF16: 2^-8 relative), everything else is FP32 arithmetic
+STEP_BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_full_size_form_step_sampled(precision):
+    """The 256^3 periodic box in each form, one igr_advance step with a
+    fixed dt (the call and launch configuration the throughput is measured
+    with: FP32 runs two-sweep passes there, the 16-bit forms single sweeps),
+    against the FP64 oracle's step of the form's stored initial state on a
+    periodic window around sampled cells."""
+    from gpu_common import window
+    w = inputs.periodic_box(n=256, seed=0)
+    banner(f"full-size {precision} step 256^3 sampled")
+    s = igr.Solver.from_workload(w, precision=precision)
+    U = s.state_from(w.U)
+    S = s.new_field()
+    U0 = to_host(s, U)                          # the stored (rounded) state, widened exactly
+    dt = 0.8 * ref.compute_dt(problem_from(w), torch.from_numpy(U0), 0.5)
+    s.advance(U, S, 1, dt_fixed=dt)
+    s.check()
+    Ug = to_host(s, U)
+    Sg = to_host(s, S)
+    R = 29                                      # three stages of the rhs dependency radius
+    n = 2 * R + 1
+    prob = ref.Problem(n, n, n, w.dx, w.dy, w.dz, alpha=w.alpha, faces=("periodic",) * 6, nsweeps=w.nsweeps)
+    scale = np.abs(Ug).reshape(5, -1).max(axis=1)
+    sscale = np.abs(Sg).max()
+    rng = np.random.default_rng(5)
+    for p in [tuple(rng.integers(0, 256, 3)) for _ in range(2)]:
+        Uw, Sw = ref.rk3_step(prob, torch.from_numpy(window(U0, p, R)), torch.zeros((n, n, n), dtype=torch.float64), dt)
+        k, j, i = p
+        err = np.abs(Ug[:, k, j, i] - Uw[:, R, R, R].numpy()) / scale
+        serr = abs(Sg[k, j, i] - float(Sw[R, R, R])) / sscale
+        print(f"[gpu-case] {precision} sample {p}: rel err (rho, mx, my, mz, E) = {err}, Sigma {serr:.2e}", flush=True)
+        assert (err <= STEP_BOUND[precision]).all(), (p, err)
+        assert serr <= STEP_BOUND[precision], (p, serr)
