@@ -56,6 +56,7 @@ def _init(grid, gamma, alpha, bc, opts):
     ("pair", igr.IGR_EINVAL), ("precision", igr.IGR_EINVAL), ("order", igr.IGR_EUNSUPPORTED),
     ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("sigma_block", igr.IGR_EINVAL),
     ("smoother", igr.IGR_EINVAL), ("rbgs_odd_periodic", igr.IGR_EUNSUPPORTED),
+    ("plane_too_large", igr.IGR_EINVAL),
 ])
 def test_init_rejects_bad_arguments(case, code):
     grid, bc, opts, gamma, alpha = _grid(), _bc(), igr.Opts(0, 5, 5, 0), 1.4, 0.01
@@ -85,6 +86,8 @@ def test_init_rejects_bad_arguments(case, code):
         grid = igr.Grid(8, 7, 8, 0.1, 0.1, 0.1)
         bc = igr.BC((ctypes.c_int32 * 6)(1, 1, 0, 0, 1, 1), 0, None)
         opts = igr.Opts(0, 5, 5, 0, 1)
+    elif case == "plane_too_large":
+        grid = igr.Grid(50000, 50000, 1, 1e-4, 1e-4, 1e-4)   # padded x-y plane beyond 32-bit offsets
     rc, h = _init(grid, gamma, alpha, bc, opts)
     assert rc == code
     assert h.value is None

@@ -248,6 +248,20 @@ def test_advance_equals_repeated_steps(case, precision):
     assert rel_linf(to_host(s, S2).astype(np.float64), to_host(s, S1).astype(np.float64)).max() <= tol
 
 
+def test_advance_zero_steps_is_a_no_op():
+    """nsteps = 0 leaves U and Sigma bitwise unchanged (no launch touches
+    them)."""
+    name, make = "mixed_70x9x7", CASES["mixed_70x9x7"]
+    w = make()
+    banner(f"advance x0 {name}")
+    s = igr.Solver.from_workload(w)
+    U = s.state_from(w.U)
+    S = s.field_from(_sigma0(w))
+    U0, S0 = U.clone(), S.clone()
+    s.advance(U, S, 0, cfl=0.5)
+    assert torch.equal(U, U0) and torch.equal(S, S0)
+
+
 def test_dt_and_sums(case):
     name, w = case
     banner(f"dt/sums {name}")
