@@ -129,10 +129,24 @@ def cpu_baseline(w, seconds_target: float = 15.0):
         el = time.perf_counter() - t0
         if el >= seconds_target or steps >= 50:
             break
-    return {"value": n ** 3 * steps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} RK3 steps of the FP64 oracle on the 128^3 periodic box (same recipe and "
-                      f"seed as the 256^3 workload), {el:.1f} s"}
+    out = {"value": n ** 3 * steps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+           "kind": "oracle",
+           "sample": f"{steps} RK3 steps of the FP64 oracle on the 128^3 periodic box (same recipe and "
+                     f"seed as the 256^3 workload), {el:.1f} s"}
+    # the same oracle on one thread: one step from the initial state
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        U1 = torch.from_numpy(ws.U)
+        sig1 = torch.zeros((n, n, n), dtype=torch.float64)
+        t0 = time.perf_counter()
+        ref.rk3_step(prob, U1, sig1, ref.compute_dt(prob, U1, w.cfl))
+        el1 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(nthreads)
+    out["single_thread"] = {"value": n ** 3 / el1, "cores": 1,
+                            "sample": f"1 RK3 step of the same 128^3 box, {el1:.1f} s"}
+    return out
 
 
 def run_form(w, precision, steps, warmup, sigma_block=0, order=5, smoother="jacobi"):
@@ -170,8 +184,9 @@ def jet_workload(n: int, nsteps: int):
 
 def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
     """Multi-jet box: rate of each precision form, device memory in use, and
-    per-field rel L1 error of the other forms against the FP64 run after
-    `nsteps` steps with the same fixed dt (computed on the GPU)."""
+    per-field rel L1 error (the six fields and the derived pressure) of the
+    other forms against the FP64 run after `nsteps` steps with the same
+    fixed dt (computed on the GPU)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
@@ -181,7 +196,7 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
            "forms": {}}
     ref = None
     dt = None
-    names = ["rho", "mx", "my", "mz", "E", "Sigma"]
+    names = ["rho", "mx", "my", "mz", "E", "Sigma", "p"]
     for prec in forms:
         print(f"[bench] multi-jet {n}^3 {prec}: building the state", file=sys.stderr, flush=True)
         s = igr.Solver.from_workload(w, precision=prec)
@@ -225,12 +240,20 @@ def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
                 out["forms"][prec] = form
                 s.close()
                 continue
-            fin = torch.cat([s.interior(U).double(), s.interior(S).double()[None]])
+            # the six fields and the derived pressure, formed in place (at
+            # 1024^3 each FP64 field is 8.6 GB)
+            fin = torch.empty((7, w.nz, w.ny, w.nx), dtype=torch.float64, device=U.device)
+            fin[:5].copy_(s.interior(U))
+            fin[5].copy_(s.interior(S))
+            pr = fin[6]
+            torch.mul(fin[1], fin[1], out=pr)
+            pr.addcmul_(fin[2], fin[2]).addcmul_(fin[3], fin[3]).div_(fin[0]).mul_(-0.5).add_(fin[4])
+            pr.mul_(w.gamma - 1.0)
             if prec == "f64":
                 ref = fin
             elif ref is not None:
                 err = [float((fin[f] - ref[f]).abs().sum() / ref[f].abs().sum()) if float(ref[f].abs().sum()) > 0
-                       else 0.0 for f in range(6)]
+                       else 0.0 for f in range(len(names))]
                 form["rel_l1_vs_f64"] = dict(zip(names, err))
             del fin
         out["forms"][prec] = form
