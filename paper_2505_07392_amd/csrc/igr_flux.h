@@ -78,7 +78,8 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const long long fs = g.fs;
     const int sy = g.st[1], sz = g.st[2];
     const C gamma = C(g.gamma);
-    const C ihx = C(g.ih[0]), ihy = C(g.ih[1]), ihz = C(g.ih[2]);
+    // face fluxes come from llf_flux scaled by 1/LLF_SCALE
+    const C ihx = LLF_SCALE<C> * C(g.ih[0]), ihy = LLF_SCALE<C> * C(g.ih[1]), ihz = LLF_SCALE<C> * C(g.ih[2]);
     const C dt = C(dtp ? *dtp : dt_fixed);
 
     // this thread's column (waves < TY): loads padded cells that exist

@@ -224,6 +224,7 @@ __device__ __forceinline__ float face_sqrt(float x) { return __builtin_amdgcn_sq
 // LLF (Rusanov) flux along axis d of eqs. (6)-(8) with tau = 0:
 // F = 1/2 (F(UL, SL) + F(UR, SR)) - 1/2 lambda (UR - UL),
 // lambda = max(|u_n| + c) of the two states (thermodynamic p only).
+// Returns F / LLF_SCALE (2F in FP32 arithmetic, F in FP64).
 template <class C>
 __device__ __forceinline__ void llf_flux(const C UL[5], const C UR[5], C SL, C SR, int d, C gamma,
                                          C F[5], bool& bad) {
@@ -239,7 +240,12 @@ __device__ __forceinline__ void llf_flux(const C UL[5], const C UR[5], C SL, C S
     const C lam = fmax(fabs(unl) + cl, fabs(unr) + cr);
     const C ptl = pl + SL;
     const C ptr = pr + SR;
-    F[0] = C(0.5) * (UL[1 + d] + UR[1 + d]) - C(0.5) * lam * (UR[0] - UL[0]);
+    // FP32 arithmetic: twice the flux, one instruction fewer per component
+    // (the kernel is issue-bound there; the factor 1/2 goes with the 1/dx
+    // of the divergence, LLF_SCALE); FP64 keeps the flux itself (the
+    // kernel is at its register limit and the other form spills)
+    constexpr C h = sizeof(C) == 4 ? C(1) : C(0.5);
+    F[0] = h * (UL[1 + d] + UR[1 + d]) - h * lam * (UR[0] - UL[0]);
     for (int c = 0; c < 3; ++c) {
         C fl = UL[1 + c] * unl;
         C fr = UR[1 + c] * unr;
@@ -247,10 +253,14 @@ __device__ __forceinline__ void llf_flux(const C UL[5], const C UR[5], C SL, C S
             fl += ptl;
             fr += ptr;
         }
-        F[1 + c] = C(0.5) * (fl + fr) - C(0.5) * lam * (UR[1 + c] - UL[1 + c]);
+        F[1 + c] = h * (fl + fr) - h * lam * (UR[1 + c] - UL[1 + c]);
     }
-    F[4] = C(0.5) * ((UL[4] + ptl) * unl + (UR[4] + ptr) * unr) - C(0.5) * lam * (UR[4] - UL[4]);
+    F[4] = h * ((UL[4] + ptl) * unl + (UR[4] + ptr) * unr) - h * lam * (UR[4] - UL[4]);
 }
+
+// Factor between llf_flux's result and the flux: 1/2 in FP32 arithmetic.
+template <class C>
+constexpr C LLF_SCALE = sizeof(C) == 4 ? C(0.5) : C(1);
 
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions: fixed grid, grid-stride loop, fixed-order
