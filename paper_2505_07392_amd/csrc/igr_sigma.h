@@ -23,6 +23,66 @@ namespace igr {
 
 constexpr int SIG_TX = 64;
 
+// One Jacobi update of the 7-point discretisation of eq. (9) at a cell,
+// in two parts: the coefficients (the face sums 1/rho_c + 1/rho_nb = 2 beta
+// and the reciprocal of the diagonal) depend on 1/rho only and are shared
+// by every sweep of a solve; the update combines them with the source and
+// the previous iterate, the factor 1/2 of beta carried with alpha/h^2 in
+// one constant per axis (loop-invariant in the callers).  ic = 1/rho of
+// the cell, ir = 1/rho and sg = the previous iterate at the x-, x+, y-,
+// y+, z-, z+ neighbours (sg already replaced by the cell's own value where
+// a zero-gradient face removes the neighbour).  Every sweep kernel goes
+// through these two functions, so equal inputs give equal bits.
+template <class C>
+struct JacCoef {
+    C bxm, bxp, bym, byp, bzm, bzp;   // 2 beta of the six faces
+    C rden;                           // 1 / (1/rho + alpha sum_d (beta_d- + beta_d+)/h_d^2)
+};
+
+// alpha / (2 h_d^2) per axis: the constants the update needs, from the
+// geometry (every kernel forms them the same way)
+template <class C>
+struct JacAxes {
+    C ax, ay, az;
+};
+template <class C>
+__device__ __forceinline__ JacAxes<C> jacobi_axes(const Geom& g) {
+    const C ha = C(0.5) * C(g.alpha);
+    return {ha * (C(g.ih[0]) * C(g.ih[0])), ha * (C(g.ih[1]) * C(g.ih[1])), ha * (C(g.ih[2]) * C(g.ih[2]))};
+}
+
+template <class C>
+__device__ __forceinline__ JacCoef<C> jacobi_coef(C ic, const C (&ir)[6], const JacAxes<C>& a) {
+    JacCoef<C> k;
+    k.bxm = ic + ir[0];
+    k.bxp = ic + ir[1];
+    k.bym = ic + ir[2];
+    k.byp = ic + ir[3];
+    k.bzm = ic + ir[4];
+    k.bzp = ic + ir[5];
+    C den = ic;
+    den += a.ax * (k.bxp + k.bxm);
+    den += a.ay * (k.byp + k.bym);
+    den += a.az * (k.bzp + k.bzm);
+    k.rden = fast_rcp(den);
+    return k;
+}
+
+template <class C>
+__device__ __forceinline__ C jacobi_apply(C bk, const JacCoef<C>& k, const C (&sg)[6], const JacAxes<C>& a) {
+    C num = bk;
+    num += a.ax * (k.bxp * sg[1] + k.bxm * sg[0]);
+    num += a.ay * (k.byp * sg[3] + k.bym * sg[2]);
+    num += a.az * (k.bzp * sg[5] + k.bzm * sg[4]);
+    return num * k.rden;
+}
+
+template <class C>
+__device__ __forceinline__ C jacobi_point(C bk, C ic, const C (&ir)[6], const C (&sg)[6], const JacAxes<C>& a) {
+    return jacobi_apply(bk, jacobi_coef(ic, ir, a), sg, a);
+}
+
+
 template <class T, int K, int NR>
 __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict__ U, const T* __restrict__ Sin,
                                                            T* __restrict__ Sout, Geom g, int tiles_x, int tiles_y,
@@ -57,8 +117,7 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
     const long long fs = g.fs;
     const int sy = g.st[1], sz = g.st[2];
     const C alpha = C(g.alpha);
-    const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
-    const C half = C(0.5);
+    const JacAxes<C> ja = jacobi_axes<C>(g);
     const C sx = C(0.5) * C(g.ih[0]), sy_ = C(0.5) * C(g.ih[1]), sz_ = C(0.5) * C(g.ih[2]);
 
     // source column in memory: periodic axes wrap, other axes clamp to the
@@ -177,21 +236,11 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
             const C syp = yhi ? sc : ls[s - 1][eyp][ex];
             const C szm = zlo ? sc : lo[s - 1];
             const C szp = zhi ? sc : newv[s - 1];
-            const C bxm = half * (ic + lr[slot][ey][exm]);
-            const C bxp = half * (ic + lr[slot][ey][exp_]);
-            const C bym = half * (ic + lr[slot][eym][ex]);
-            const C byp = half * (ic + lr[slot][eyp][ex]);
-            const C bzm = half * (ic + irR[2 + s]);
-            const C bzp = half * (ic + irR[s]);
-            C num = bR[s - 1];   // b at plane P-1-s (bR is shifted at the end of the iteration)
-            C den = ic;
-            num += alpha * (bxp * sxp + bxm * sxm) * hx2;
-            den += alpha * (bxp + bxm) * hx2;
-            num += alpha * (byp * syp + bym * sym) * hy2;
-            den += alpha * (byp + bym) * hy2;
-            num += alpha * (bzp * szp + bzm * szm) * hz2;
-            den += alpha * (bzp + bzm) * hz2;
-            newv[s] = num / den;
+            const C irv[6] = {lr[slot][ey][exm], lr[slot][ey][exp_], lr[slot][eym][ex],
+                              lr[slot][eyp][ex], irR[2 + s],         irR[s]};
+            const C sgv[6] = {sxm, sxp, sym, syp, szm, szp};
+            // b at plane P-1-s (bR is shifted at the end of the iteration)
+            newv[s] = jacobi_point(bR[s - 1], ic, irv, sgv, ja);
         }
         __syncthreads();
         // ---- phase W: publish planes for the next iteration
@@ -220,60 +269,6 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
         }
         __syncthreads();
     }
-}
-
-}  // namespace igr
-
-namespace igr {
-
-// One Jacobi update of the 7-point discretisation of eq. (9) at a cell,
-// in two parts: the coefficients (face coefficients beta = (1/rho_c +
-// 1/rho_nb)/2 scaled by alpha/h^2, and the reciprocal of the diagonal)
-// depend on 1/rho only and are shared by every sweep of a solve; the
-// update combines them with the source and the previous iterate.  ic =
-// 1/rho of the cell, ir = 1/rho and sg = the previous iterate at the x-,
-// x+, y-, y+, z-, z+ neighbours (sg already replaced by the cell's own
-// value where a zero-gradient face removes the neighbour).  Every sweep
-// kernel goes through these two functions, so equal inputs give equal
-// bits.
-template <class C>
-struct JacCoef {
-    C bxm, bxp, bym, byp, bzm, bzp;   // beta of the six faces
-    C rden;                           // 1 / (1/rho + alpha sum_d (beta_d- + beta_d+)/h_d^2)
-};
-
-template <class C>
-__device__ __forceinline__ JacCoef<C> jacobi_coef(C ic, const C (&ir)[6], C alpha, C hx2, C hy2, C hz2) {
-    const C half = C(0.5);
-    JacCoef<C> k;
-    k.bxm = half * (ic + ir[0]);
-    k.bxp = half * (ic + ir[1]);
-    k.bym = half * (ic + ir[2]);
-    k.byp = half * (ic + ir[3]);
-    k.bzm = half * (ic + ir[4]);
-    k.bzp = half * (ic + ir[5]);
-    C den = ic;
-    den += alpha * (k.bxp + k.bxm) * hx2;
-    den += alpha * (k.byp + k.bym) * hy2;
-    den += alpha * (k.bzp + k.bzm) * hz2;
-    k.rden = fast_rcp(den);
-    return k;
-}
-
-template <class C>
-__device__ __forceinline__ C jacobi_apply(C bk, const JacCoef<C>& k, const C (&sg)[6], C alpha, C hx2, C hy2,
-                                          C hz2) {
-    C num = bk;
-    num += alpha * (k.bxp * sg[1] + k.bxm * sg[0]) * hx2;
-    num += alpha * (k.byp * sg[3] + k.bym * sg[2]) * hy2;
-    num += alpha * (k.bzp * sg[5] + k.bzm * sg[4]) * hz2;
-    return num * k.rden;
-}
-
-template <class C>
-__device__ __forceinline__ C jacobi_point(C bk, C ic, const C (&ir)[6], const C (&sg)[6], C alpha, C hx2, C hy2,
-                                          C hz2) {
-    return jacobi_apply(bk, jacobi_coef(ic, ir, alpha, hx2, hy2, hz2), sg, alpha, hx2, hy2, hz2);
 }
 
 // One Jacobi sweep per pass, z-marching: a 64 x SWEEP_RY block of columns walks a
@@ -345,7 +340,7 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
     const int sy = g.st[1], sz = g.st[2];
     const long long col = (long long)(j + G) * sy + (i + G);
     const C alpha = C(g.alpha);
-    const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
+    const JacAxes<C> ja = jacobi_axes<C>(g);
     // x/y neighbours: rho from the padded array, Sigma with wrap or self
     const int onb[4] = {-1, 1, -sy, sy};
     const int osg[4] = {neighbour_no_ghost(g, 0, i, -1), neighbour_no_ghost(g, 0, i, +1),
@@ -474,7 +469,7 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
         // with even periodic extents every neighbour read here has the
         // other colour, so no value this launch writes is read by it)
         if (colour < 0 || ((i + j + k) & 1) == colour)
-            S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, alpha, hx2, hy2, hz2));
+            S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, ja));
         ir_m = ir_c;
         ir_c = ir_p;
         s_m = s_c;
@@ -657,7 +652,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     const bool xlo = !px && gx == 0, xhi = !px && gx == nx - 1;
     const bool ylo = !py && gy == 0, yhi = !py && gy == ny - 1;
     const C alpha = C(g.alpha);
-    const C hx2 = C(g.ih[0]) * C(g.ih[0]), hy2 = C(g.ih[1]) * C(g.ih[1]), hz2 = C(g.ih[2]) * C(g.ih[2]);
+    const JacAxes<C> ja = jacobi_axes<C>(g);
     const int cx = lx + 2, cy = ly + 1;       // input-ring coordinates of the own column
     const int xr = ly == 0 ? 0 : NR + 1;      // input-ring row of the ring-2 row
     const int bxc = lx + 1;                   // b / level-1 column
@@ -724,7 +719,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
             const C sgv[6] = {xlo ? sc : ls0[a4][cy][cx - 1], xhi ? sc : ls0[a4][cy][cx + 1],
                               ylo ? sc : ls0[a4][cy - 1][cx], yhi ? sc : ls0[a4][cy + 1][cx],
                               (!pz && z == 0) ? sc : ls0[m4][cy][cx], (!pz && z == nz - 1) ? sc : ls0[w4][cy][cx]};
-            kn = jacobi_coef(lir[a4][cy][cx], irv, alpha, hx2, hy2, hz2);
+            kn = jacobi_coef(lir[a4][cy][cx], irv, ja);
             if constexpr (FIRST) {
                 // source at this cell, eq. (9) left side
                 const int a3 = (P + 5) % 3;
@@ -760,7 +755,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
             } else {
                 bn = lb[(P + 5) % 3][ly][bxc];
             }
-            v1 = jacobi_apply(bn, kn, sgv, alpha, hx2, hy2, hz2);
+            v1 = jacobi_apply(bn, kn, sgv, ja);
             ls1[(P + 7) & 1][ly][bxc] = v1;
         }
         // level 2 (output) at plane P-2, with the coefficients and source
@@ -772,7 +767,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
             const C sgv[6] = {xlo ? sc : ls1[a2][ly][lx], xhi ? sc : ls1[a2][ly][lx + 2],
                               ylo ? sc : ls1[a2][ly - 1][bxc], yhi ? sc : ls1[a2][ly + 1][bxc],
                               (!pz && z2 == 0) ? sc : qs1[0], (!pz && z2 == nz - 1) ? sc : v1};
-            const C v2 = jacobi_apply(bprev, kc, sgv, alpha, hx2, hy2, hz2);
+            const C v2 = jacobi_apply(bprev, kc, sgv, ja);
             S::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
         }
         kc = kn;
