@@ -78,11 +78,14 @@ struct Storage<f16> {
     __device__ __forceinline__ static C stored(C v) { return float(f16(v)); }
 };
 
-// Reciprocal for finite positive arguments: the hardware estimate refined by
-// Newton steps (two in FP64, one in FP32) -- within an ulp or two of the
-// correctly rounded quotient at a third of the instructions of IEEE
-// division.  Non-positive or non-finite arguments only occur for states
-// the kernels already flag as non-physical.
+// Reciprocal for finite positive arguments.  FP64: the hardware estimate
+// refined by two Newton steps, within an ulp or two of the correctly
+// rounded quotient at a third of the instructions of IEEE division.  FP32
+// (the arithmetic of the precision forms, whose kernels are bound by
+// instruction issue): the hardware estimate alone, accurate to about one
+// ulp (a Newton step measured 1.5-2 % slower per step and changes nothing
+// at the forms' error level).  Non-positive or non-finite arguments only
+// occur for states the kernels already flag as non-physical.
 __device__ __forceinline__ double fast_rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = __builtin_fma(-x, r, 1.0);
@@ -90,11 +93,7 @@ __device__ __forceinline__ double fast_rcp(double x) {
     e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
 }
-__device__ __forceinline__ float fast_rcp(float x) {
-    float r = __builtin_amdgcn_rcpf(x);
-    const float e = __builtin_fmaf(-x, r, 1.0f);
-    return __builtin_fmaf(r, e, r);
-}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Block index -> logical tile index such that consecutive logical tiles run
 // on the same XCD (blocks are dealt round-robin to the 8 XCDs), so a tile's
