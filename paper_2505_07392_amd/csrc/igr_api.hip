@@ -256,9 +256,42 @@ int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
 // temporally blocked kernel that forms the source itself.  The last
 // iterate ends in `sig` (device copy after an odd number of passes) and
 // its ghosts are filled.
+#ifndef IGR_SWEEP_BLOCKS
+#define IGR_SWEEP_BLOCKS 2048
+#endif
+#ifndef IGR_SWEEP_ZC_MIN
+#define IGR_SWEEP_ZC_MIN 4
+#endif
+// Single-sweep launch: 64 x ry column tiles, z chunks sized for about
+// IGR_SWEEP_BLOCKS blocks.
+struct SweepShape {
+    int tiles_x, tiles_y, zc;
+    long long blocks;
+};
+SweepShape sweep_shape(const Geom& g, int ry) {
+    SweepShape sh;
+    sh.tiles_x = (g.n[0] + 63) / 64;
+    sh.tiles_y = (g.n[1] + ry - 1) / ry;
+    const long long tiles = (long long)sh.tiles_x * sh.tiles_y;
+    long long zc = (tiles * g.n[2] + IGR_SWEEP_BLOCKS - 1) / IGR_SWEEP_BLOCKS;
+    if (zc < IGR_SWEEP_ZC_MIN) zc = IGR_SWEEP_ZC_MIN;
+    if (zc > 64) zc = 64;
+    if (zc > g.n[2]) zc = g.n[2];
+    sh.zc = int(zc);
+    sh.blocks = tiles * ((g.n[2] + zc - 1) / zc);
+    return sh;
+}
+// CFL maxima left by a first sweep that forms them: one per wave.
+long long sweep_speed_slots(const Geom& g) { return sweep_shape(g, SWEEP_RY_FIRST).blocks * SWEEP_RY_FIRST; }
+
+// speed (FP64 contexts, nullable): if the solve starts with a single first
+// sweep, that sweep also leaves the CFL maxima of U there and *nspeed is
+// their count; otherwise *nspeed is 0.
 template <class T>
-int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, hipStream_t s) {
+int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, hipStream_t s,
+                    double* speed = nullptr, int* nspeed = nullptr) {
     using C = typename Storage<T>::C;
+    if (nspeed) *nspeed = 0;
     T* src = in;
     T* dst = other;
     auto swap = [&] {
@@ -268,44 +301,29 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
     };
     if (c->sigma_block <= 2 || c->smoother == IGR_SMOOTH_RBGS) {
         const Geom& g = c->g;
-#ifndef IGR_SWEEP_BLOCKS
-#define IGR_SWEEP_BLOCKS 2048
-#endif
-#ifndef IGR_SWEEP_ZC_MIN
-#define IGR_SWEEP_ZC_MIN 4
-#endif
-        // 64 x ry column tiles, z chunks sized for about IGR_SWEEP_BLOCKS blocks
-        struct Shape {
-            int tiles_x, tiles_y, zc;
-            long long blocks;
-        };
-        auto shape = [&](int ry) {
-            Shape sh;
-            sh.tiles_x = (g.n[0] + 63) / 64;
-            sh.tiles_y = (g.n[1] + ry - 1) / ry;
-            const long long tiles = (long long)sh.tiles_x * sh.tiles_y;
-            long long zc = (tiles * g.n[2] + IGR_SWEEP_BLOCKS - 1) / IGR_SWEEP_BLOCKS;
-            if (zc < IGR_SWEEP_ZC_MIN) zc = IGR_SWEEP_ZC_MIN;
-            if (zc > 64) zc = 64;
-            if (zc > g.n[2]) zc = g.n[2];
-            sh.zc = int(zc);
-            sh.blocks = tiles * ((g.n[2] + zc - 1) / zc);
-            return sh;
-        };
-        const Shape sf = shape(SWEEP_RY_FIRST), sl = shape(SWEEP_RY);
+        const SweepShape sf = sweep_shape(g, SWEEP_RY_FIRST), sl = sweep_shape(g, SWEEP_RY);
         if (sf.blocks > 0x7fffffffLL || sl.blocks > 0x7fffffffLL)
             return fail(IGR_EINVAL, "grid too large for the sweep launch");
         C* b = static_cast<C*>(c->d_b);
         C* ir = static_cast<C*>(c->d_ir);
         auto single = [&](bool first, int colour = -1) {
             T* out = colour < 0 ? dst : src;   // red-black half-sweeps work in place
+            constexpr bool SPD_OK = sizeof(C) == 8;   // CFL maxima formed in the first sweep: FP64
+            const bool spd = SPD_OK && first && speed != nullptr;
+            if (spd && nspeed) *nspeed = int(sf.blocks * SWEEP_RY_FIRST);
             return launch(c, K_JACOBI, s, [&] {
-                if (first)
+                if (first && spd) {
+                    if constexpr (SPD_OK)
+                        k_sweep_z<T, true, SWEEP_RY_FIRST, true>
+                            <<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
+                                U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, speed, c->d_flag);
+                } else if (first) {
                     k_sweep_z<T, true, SWEEP_RY_FIRST><<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
-                        U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour);
-                else
+                        U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, nullptr, nullptr);
+                } else {
                     k_sweep_z<T, false, SWEEP_RY><<<dim3(unsigned(sl.blocks)), dim3(64, SWEEP_RY), 0, s>>>(
-                        U, src, out, b, ir, g, sl.zc, sl.tiles_x, sl.tiles_y, colour);
+                        U, src, out, b, ir, g, sl.zc, sl.tiles_x, sl.tiles_y, colour, nullptr, nullptr);
+                }
             });
         };
         if (c->smoother == IGR_SMOOTH_RBGS) {
@@ -482,16 +500,19 @@ int rhs_impl(igr_ctx* c, T* U, T* sig, T* rhs, hipStream_t s) {
 // dt_fixed; with `speed` the last stage also leaves the per-block CFL
 // maxima of the new state there (one value per flux block).
 template <class T>
-int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hipStream_t s, double* speed) {
+// With cfl_dt the time step is the CFL step of U, formed in stage 1
+// (dtp is then ignored).
+int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hipStream_t s, double* speed,
+                bool cfl_dt = false, double cfl = 0.0) {
     T* Ua = static_cast<T*>(c->d_Ua);
     T* Ub = static_cast<T*>(c->d_Ub);
     // Sigma ping-pongs between the caller's buffer and the scratch copy
     // across the three stages; one copy at the end if it ends in scratch
     T* cur = sig;
     T* oth = static_cast<T*>(c->d_sig2);
-    auto solve = [&](T* Us) -> int {
+    auto solve = [&](T* Us, double* spd = nullptr, int* nspd = nullptr) -> int {
         T* res = nullptr;
-        IGR_TRY(sigma_solve_buf(c, Us, cur, oth, c->nsweeps, &res, s));
+        IGR_TRY(sigma_solve_buf(c, Us, cur, oth, c->nsweeps, &res, s, spd, nspd));
         if (res != cur) {
             oth = cur;
             cur = res;
@@ -500,7 +521,22 @@ int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hi
     };
     // stage 1: U1 = Un + dt L(Un)
     IGR_TRY(fill_state_ghosts(c, U, s));
-    IGR_TRY(solve(U));
+    if (cfl_dt) {
+        // dt from Un: the first sweep of this solve forms the CFL maxima
+        // when it can (FP64, solve starting with a single sweep), else the
+        // standalone reduction runs; either way before the flux needs dt
+        int nspd = 0;
+        IGR_TRY(solve(U, c->d_speed, &nspd));
+        if (nspd > 0)
+            IGR_TRY(launch(c, K_DT, s, [&] {
+                k_dt_final<<<1, RED_THREADS, 0, s>>>(c->d_speed, nspd, cfl, c->d_scalars);
+            }));
+        else
+            IGR_TRY(speed_dt_impl(c, U, cfl, s));
+        dtp = c->d_scalars;
+    } else {
+        IGR_TRY(solve(U));
+    }
     IGR_TRY((flux_impl<T, MODE_STAGE1>(c, U, cur, nullptr, Ua, dtp, dt_fixed, s)));
     // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
     IGR_TRY(fill_state_ghosts(c, Ua, s));
@@ -517,20 +553,15 @@ int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hi
 
 template <class T>
 int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t s) {
-    const double* dtp = nullptr;
-    if (!(dt_fixed > 0.0)) {
-        IGR_TRY(speed_dt_impl(c, U, cfl, s));
-        dtp = c->d_scalars;
-    }
-    return step_stages(c, U, sig, dtp, dt_fixed, s, nullptr);
+    if (!(dt_fixed > 0.0)) return step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr, true, cfl);
+    return step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr);
 }
 
-// nsteps steps; with a CFL time step, the first step's maximum comes from
-// the standalone reduction and every later one from the maxima that the
-// previous step's last stage left in d_speed.  The fusion is compiled for
-// the forms with FP32 arithmetic only (the FP64 flux kernel is at its
-// register limit, and spilling there costs what the separate pass does):
-// FP64 runs the standalone reduction before every step.
+// nsteps steps.  With a CFL time step in the forms with FP32 arithmetic,
+// the first step's maximum comes from the standalone reduction and every
+// later one from the maxima that the previous step's last stage left in
+// d_speed.  FP64 forms each step's maxima in its first sweep instead (the
+// FP64 flux kernel is at its register limit: fused there it spills).
 template <class T>
 int advance_impl(igr_ctx* c, T* U, T* sig, int nsteps, double cfl, double dt_fixed, hipStream_t s) {
     const bool use_cfl = !(dt_fixed > 0.0);
@@ -538,8 +569,12 @@ int advance_impl(igr_ctx* c, T* U, T* sig, int nsteps, double cfl, double dt_fix
     const int nblk = int(flux_blocks<T>(c));
     for (int n = 0; n < nsteps; ++n) {
         const double* dtp = nullptr;
+        if (use_cfl && !fused) {
+            IGR_TRY(step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr, true, cfl));
+            continue;
+        }
         if (use_cfl) {
-            if (n == 0 || !fused) {
+            if (n == 0) {
                 IGR_TRY(speed_dt_impl(c, U, cfl, s));
             } else {
                 IGR_TRY(launch(c, K_DT, s, [&] {
@@ -950,7 +985,10 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
     if (!rc) {
-        const long long nb = c->precision == IGR_F64 ? flux_blocks<double>(c) : flux_blocks<float>(c);
+        // per-block CFL maxima: of the last flux stage (FP32 arithmetic) or
+        // of the first sweep (FP64)
+        long long nb = c->precision == IGR_F64 ? flux_blocks<double>(c) : flux_blocks<float>(c);
+        if (c->precision == IGR_F64 && sweep_speed_slots(c->g) > nb) nb = sweep_speed_slots(c->g);
         rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
     }
     if (!rc && !c->patches.empty()) {

@@ -294,6 +294,7 @@ struct SweepCol {
     R rho, sig;         // rho, Sigma_in at plane k+1
     C b;                // b at plane k (later sweeps)
     R m[3];             // m at plane k+1 (FIRST)
+    R E;                // E at plane k+1 (first sweep that also forms the CFL maxima)
 };
 template <class T, bool FIRST>
 struct SweepNb {
@@ -311,11 +312,18 @@ struct SweepNb {
 constexpr int SWEEP_RY = IGR_SWEEP_RY;               // rows of a later-sweep block (64 x SWEEP_RY)
 constexpr int SWEEP_RY_FIRST = IGR_SWEEP_RY_FIRST;   // rows of a first-sweep block
 
-template <class T, bool FIRST, int RY>
+// With SPD (first sweep only) the kernel also reads E and forms the CFL
+// speed of every cell of its chunk of the state it sweeps from (cfl_speed,
+// the expression of the standalone reduction, on the stored values); each
+// wave leaves its maximum in speed[blockIdx.x * RY + wave] and non-physical
+// states raise *flag, so the time step of the stage needs no separate pass.
+template <class T, bool FIRST, int RY, bool SPD = false>
 __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, const T* Sin, T* Sout,
                                                  typename Storage<T>::C* __restrict__ b,
                                                  typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
-                                                 int tiles_x, int tiles_y, int colour) {
+                                                 int tiles_x, int tiles_y, int colour,
+                                                 double* __restrict__ speed, int* __restrict__ flag) {
+    static_assert(!SPD || FIRST, "the CFL maxima need the first sweep's state loads");
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
@@ -334,7 +342,11 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
     const int j = by * RY + threadIdx.y;
     const int z0 = bz * zc;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    if (i >= nx || j >= ny) return;
+    double smax = 0.0;   // SPD: CFL maximum of this thread's cells
+    bool bad = false;
+    // lanes outside the grid skip the sweep (no early return: with SPD every
+    // lane takes part in the wave's reduction at the end)
+    if (i < nx && j < ny) {
     const int z1 = min(z0 + zc, nz);
     const long long fs = g.fs;
     const int sy = g.st[1], sz = g.st[2];
@@ -364,6 +376,7 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
         } else {
             P.b = b[zplane(k)];
         }
+        if constexpr (SPD) P.E = S::load_raw(U + 4 * fs + op);
     };
     auto load_nb = [&](int k, SweepNb<T, FIRST>& P) {
         const long long o = zplane(k);
@@ -401,6 +414,11 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
             u_m[c] = S::load(U + (1 + c) * fs + zplane(z0 - 1)) * ir_m;
             u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
         }
+    }
+    if constexpr (SPD) {   // plane z0; the loop adds plane k+1 < z1 at iteration k
+        const long long o0 = zplane(z0);
+        smax = cfl_speed(g, double(S::load(U + o0)), double(S::load(U + fs + o0)), double(S::load(U + 2 * fs + o0)),
+                         double(S::load(U + 3 * fs + o0)), double(S::load(U + 4 * fs + o0)), bad);
     }
     // Loads are unconditional (planes clamped to the chunk) and issued in
     // the order they are needed -- the neighbours of the next plane first,
@@ -470,6 +488,12 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
         // other colour, so no value this launch writes is read by it)
         if (colour < 0 || ((i + j + k) & 1) == colour)
             S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, ja));
+        if constexpr (SPD) {
+            if (k + 1 < z1)
+                smax = fmax(smax, cfl_speed(g, double(S::cvt(cc.rho)), double(S::cvt(cc.m[0])),
+                                            double(S::cvt(cc.m[1])), double(S::cvt(cc.m[2])),
+                                            double(S::cvt(cc.E)), bad));
+        }
         ir_m = ir_c;
         ir_c = ir_p;
         s_m = s_c;
@@ -482,6 +506,12 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
             }
         }
         cur = nxt;
+    }
+    }
+    if constexpr (SPD) {
+        for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+        if (threadIdx.x == 0) speed[(long long)blockIdx.x * RY + threadIdx.y] = smax;
+        if (bad) flag[0] = 1;
     }
 }
 

@@ -248,6 +248,26 @@ def test_advance_equals_repeated_steps(case, precision):
     assert rel_linf(to_host(s, S2).astype(np.float64), to_host(s, S1).astype(np.float64)).max() <= tol
 
 
+@pytest.mark.parametrize("nsweeps,smoother", [(5, "jacobi"), (4, "jacobi"), (1, "jacobi"), (3, "rbgs")])
+def test_cfl_dt_of_a_step_equals_the_standalone_reduction(nsweeps, smoother):
+    """FP64 steps form the CFL maxima in the first sweep of the first Sigma
+    solve when that solve starts with a single sweep (odd counts, red-black)
+    and fall back to the separate pass otherwise (even counts start with a
+    two-sweep pass): the time step is bitwise the standalone one."""
+    w = _mixed_workload(20, 40, 10, 6, faces=("extrap", "extrap", "periodic", "periodic", "periodic", "periodic"))
+    banner(f"cfl dt fused vs standalone nsweeps={nsweeps} {smoother}")
+    s = igr.Solver.from_workload(w, nsweeps=nsweeps, smoother=smoother)
+    U = s.state_from(w.U)
+    S = s.field_from(_sigma0(w))
+    for _ in range(2):
+        want = s.compute_dt(U, 0.5)
+        got = s.step(U, S, cfl=0.5)
+        assert got == want, (got, want)
+    want = s.compute_dt(U, 0.5)
+    got = s.advance(U, S, 1, cfl=0.5)
+    assert got == want, (got, want)
+
+
 def test_advance_zero_steps_is_a_no_op():
     """nsteps = 0 leaves U and Sigma bitwise unchanged (no launch touches
     them)."""
