@@ -110,15 +110,19 @@ int launch(igr_ctx* c, int kernel, hipStream_t s, F&& fn) {
     if (c->timing) {
         rec.start = pooled_event(c);
         rec.stop = pooled_event(c);
-        if (rec.start) hipEventRecord(rec.start, s);
     }
+    // a launch whose events cannot be recorded is simply not timed
+    bool timed = rec.start && rec.stop && hipEventRecord(rec.start, s) == hipSuccess;
     fn();
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(IGR_EHIP, std::string("launch of ") + kKernelNames[kernel] + ": " + hipGetErrorString(e));
-    if (c->timing && rec.start && rec.stop) {
-        hipEventRecord(rec.stop, s);
+    timed = timed && e == hipSuccess && hipEventRecord(rec.stop, s) == hipSuccess;
+    if (timed) {
         c->records.push_back(rec);
+    } else {   // unused events go back to the pool
+        if (rec.start) c->event_pool.push_back(rec.start);
+        if (rec.stop) c->event_pool.push_back(rec.stop);
     }
+    if (e != hipSuccess) return fail(IGR_EHIP, std::string("launch of ") + kKernelNames[kernel] + ": " + hipGetErrorString(e));
     return IGR_OK;
 }
 
@@ -1018,8 +1022,9 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
 
 int igr_finalize(igr_ctx* ctx) {
     if (!ctx) return IGR_OK;
-    hipDeviceSynchronize();
+    const hipError_t e = hipDeviceSynchronize();   // pending work may still use the scratch
     release(ctx);
+    if (e != hipSuccess) return fail(IGR_EHIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
     return IGR_OK;
 }
 

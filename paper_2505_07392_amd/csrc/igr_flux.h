@@ -64,7 +64,6 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 
     const int lane = threadIdx.x;
     const int wv = threadIdx.y;
-    const int nthreads = TX * (TY + 1);
     const int tid = wv * TX + lane;
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % tiles_x;
