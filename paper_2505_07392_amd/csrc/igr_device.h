@@ -9,17 +9,13 @@ namespace igr {
 constexpr int G = 3;  // ghost layers (five-point upwind reconstruction)
 
 // bfloat16 storage word.  Values are widened to float for arithmetic and
-// rounded back to nearest-even once per store.
+// rounded back to nearest-even once per store (gfx950's conversion
+// instruction, in the default rounding mode).
 struct bf16 {
     uint16_t bits;
 };
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x0040u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 // Storage type T -> arithmetic type C with load/store conversions.  R is
 // the register form of a loaded value before conversion: kernels that load
