@@ -126,17 +126,33 @@ int launch(igr_ctx* c, int kernel, hipStream_t s, F&& fn) {
     return IGR_OK;
 }
 
+// Folds the recorded launch times into the per-kernel totals.  The records
+// leave the context first, and every record's two events go back to the
+// pool exactly once, also when a query fails part way (the failed record
+// and the ones after it are then dropped untimed).
 int collect_timing(igr_ctx* c) {
-    for (auto& r : c->records) {
-        IGR_HIP(hipEventSynchronize(r.stop));
-        float ms = 0.f;
-        IGR_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
-        c->kernel_ms[r.kernel] += ms;
-        c->kernel_count[r.kernel] += 1;
+    std::vector<TimingRecord> recs;
+    recs.swap(c->records);
+    hipError_t err = hipSuccess;
+    const char* what = "";
+    for (const TimingRecord& r : recs) {
+        if (err == hipSuccess) {
+            float ms = 0.f;
+            err = hipEventSynchronize(r.stop);
+            what = "hipEventSynchronize";
+            if (err == hipSuccess) {
+                err = hipEventElapsedTime(&ms, r.start, r.stop);
+                what = "hipEventElapsedTime";
+            }
+            if (err == hipSuccess) {
+                c->kernel_ms[r.kernel] += ms;
+                c->kernel_count[r.kernel] += 1;
+            }
+        }
         c->event_pool.push_back(r.start);
         c->event_pool.push_back(r.stop);
     }
-    c->records.clear();
+    if (err != hipSuccess) return fail(IGR_EHIP, std::string(what) + ": " + hipGetErrorString(err));
     return IGR_OK;
 }
 
@@ -878,6 +894,7 @@ void jet_primitive_bar(const igr_ctx* c, const std::vector<double>& jbar, double
     }
 }
 
+
 }  // namespace
 
 extern "C" {
@@ -1238,5 +1255,6 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     if (patch_bar) jet_primitive_bar(ctx, jbar, patch_bar);
     return IGR_OK;
 }
+
 
 }  // extern "C"

@@ -171,3 +171,44 @@ def test_full_size_form_step_sampled(precision):
         print(f"[gpu-case] {precision} sample {p}: rel err (rho, mx, my, mz, E) = {err}, Sigma {serr:.2e}", flush=True)
         assert (err <= STEP_BOUND[precision]).all(), (p, err)
         assert serr <= STEP_BOUND[precision], (p, serr)
+
+
+def test_bf16_store_rounds_to_nearest_even():
+    """BF16 stores round to nearest even.  Inside a sharp inflow disc
+    (chi = 1) the stored ghost is the jet's conserved state converted to
+    FP32 and then to BF16, with no other arithmetic in between; jet
+    densities at BF16 ties (1 + 2^-8 rounds down to even, 1 + 3 * 2^-8 up
+    to even) and just above a tie must give exactly the bits of torch's
+    float32 -> bfloat16 conversion (round to nearest even)."""
+    banner("bf16 rounding of the jet ghost at ties")
+    n = 16
+    dx = 1.0 / n
+    rhos = [1.0 + 2.0 ** -8, 1.0 + 3.0 * 2.0 ** -8, 1.0 + 3.0 * 2.0 ** -8 + 2.0 ** -16]
+    centres = [(0.25, 0.25), (0.75, 0.25), (0.5, 0.75)]
+    jets = [inputs.Jet(yc=yc, zc=zc, r=1.5 * dx, rho=r, ux=1.0, uy=-1.0, uz=0.0, p=0.75)
+            for (yc, zc), r in zip(centres, rhos)]
+    w = inputs.Workload("ties", 8, n, n, dx, dx, dx, inputs.random_state(8, n, n, seed=1), alpha=0.0,
+                        jets=jets, nsweeps=0)
+    s = igr.Solver.from_workload(w, precision="bf16")
+    U = s.state_from(w.U)
+    S = s.new_field()
+    s.sigma_solve(U, S, nsweeps=0)            # fills the state's ghosts
+    torch.cuda.synchronize()
+    G = igr.G
+    checked = 0
+    for q, jt in enumerate(jets):
+        cons = torch.tensor([jt.rho, jt.rho * jt.ux, jt.rho * jt.uy, jt.rho * jt.uz,
+                             jt.p / (w.gamma - 1.0) + 0.5 * jt.rho * (jt.ux ** 2 + jt.uy ** 2 + jt.uz ** 2)],
+                            dtype=torch.float64)
+        want = cons.float().bfloat16().view(torch.int16)
+        for k in range(n):
+            for j in range(n):
+                y, z = (j + 0.5) * dx, (k + 0.5) * dx
+                if (y - jt.yc) ** 2 + (z - jt.zc) ** 2 > jt.r ** 2:
+                    continue
+                got = U[:, k + G, j + G, :G].cpu().view(torch.int16)
+                for layer in range(G):
+                    assert torch.equal(got[:, layer], want), (q, j, k, layer, got[:, layer], want)
+                checked += 1
+    assert checked >= 3 * 4
+    s.close()
