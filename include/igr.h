@@ -234,6 +234,25 @@ int igr_step_adjoint(igr_ctx *ctx, void *U_n, const void *sigma_n, double dt, co
 /* FP64 CFL time step of state U (rule as in igr_step; synchronises). */
 int igr_compute_dt(igr_ctx *ctx, const void *U, double cfl, double *dt, void *stream);
 
+/* igr_compute_dt without a context, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same FP64 CFL time step as
+ * igr_compute_dt for a state U of the padded layout above, described by
+ * grid, gamma (> 1) and precision (one of the IGR_* storage forms); U is
+ * only read and may hold any ghost values.  The call allocates nothing:
+ * its reduction partials, result and non-finite flag live in a fixed
+ * 16 KiB device array of the library (one per device, held until the
+ * process ends), located once per device on the first call with that
+ * device current.  The reduction runs on a fixed grid of 1024 blocks, so
+ * every grid whose x-y plane fits 32-bit offsets fits the array (larger
+ * planes: IGR_EINVAL).  The flag is cleared by a kernel at the start of
+ * each call; the stream is synchronised and *dt receives the step;
+ * IGR_ENONFINITE reports rho <= 0, p <= 0 or a non-finite value.  All
+ * calls on one device share the array: calls that overlap on one device
+ * (on different streams or host threads) race and must not be issued. */
+int igr_compute_dt_noalloc(const igr_grid *grid, double gamma, int32_t precision, const void *U, double cfl,
+                           double *dt, void *stream);
+
 /* FP64 totals sum_cells U dV of the five conserved variables in a fixed
  * reduction order (synchronises). */
 int igr_sums(igr_ctx *ctx, const void *U, double out[5], void *stream);

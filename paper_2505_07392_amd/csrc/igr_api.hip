@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -895,6 +896,62 @@ void jet_primitive_bar(const igr_ctx* c, const std::vector<double>& jbar, double
 }
 
 
+// ---------------------------------------------------------------------------
+// Allocation-free CFL time step (igr_compute_dt_noalloc)
+// ---------------------------------------------------------------------------
+
+// Scratch of the allocation-free entry point: RED_BLOCKS FP64 partial maxima,
+// the FP64 result and the non-finite flag.  Each device the library runs on
+// holds its own copy until the process ends.  In host code this name is a
+// host-side stand-in, never a device address: host code uses the address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocPartialOff = 0;
+constexpr size_t kNoAllocResultOff = RED_BLOCKS * sizeof(double);
+constexpr size_t kNoAllocFlagOff = kNoAllocResultOff + sizeof(double);
+constexpr size_t kNoAllocBytes = 16384;
+static_assert(kNoAllocFlagOff + sizeof(int) <= kNoAllocBytes, "scratch too small for the reduction");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+__global__ void k_clear_flag(int* flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+unsigned char* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    IGR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(IGR_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        IGR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(IGR_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_noalloc_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return IGR_OK;
+}
+
+template <class T>
+int dt_noalloc_t(const Geom& g, const void* U, double* partial, double* result, int* flag, double cfl,
+                 hipStream_t s) {
+    k_clear_flag<<<1, 64, 0, s>>>(flag);
+    k_speed_partial<T><<<RED_BLOCKS, RED_THREADS, 0, s>>>(static_cast<const T*>(U), g, partial, flag);
+    k_dt_final<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, cfl, result);
+    IGR_HIP(hipGetLastError());
+    return IGR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1256,5 +1313,49 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     return IGR_OK;
 }
 
+
+int igr_compute_dt_noalloc(const igr_grid* grid, double gamma, int32_t precision, const void* U, double cfl,
+                           double* dt, void* stream) {
+    if (!grid || !U || !dt) return fail(IGR_EINVAL, "null argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(IGR_EINVAL, "grid extents must be >= 1");
+    if (!(grid->dx > 0) || !(grid->dy > 0) || !(grid->dz > 0)) return fail(IGR_EINVAL, "spacings must be > 0");
+    if (!(gamma > 1.0)) return fail(IGR_EINVAL, "gamma must be > 1");
+    if (!(cfl > 0.0)) return fail(IGR_EINVAL, "cfl must be > 0");
+    if (precision != IGR_F64 && precision != IGR_F32 && precision != IGR_BF16_F32 && precision != IGR_F16_F32)
+        return fail(IGR_EINVAL, "unknown precision");
+    const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;
+    if (px * py > 0x7fffffffLL) return fail(IGR_EINVAL, "x-y plane too large");
+    // the reduction runs on a fixed grid of RED_BLOCKS blocks whatever the
+    // extents, so its partials always fit the scratch
+    if (kNoAllocFlagOff + sizeof(int) > kNoAllocBytes) return fail(IGR_EINVAL, "reduction exceeds the scratch");
+    Geom g{};
+    g.n[0] = grid->nx;
+    g.n[1] = grid->ny;
+    g.n[2] = grid->nz;
+    g.st[0] = 1;
+    g.st[1] = int(px);
+    g.st[2] = int(px * py);
+    g.fs = px * py * pz;
+    g.ih[0] = 1.0 / grid->dx;
+    g.ih[1] = 1.0 / grid->dy;
+    g.ih[2] = 1.0 / grid->dz;
+    g.gamma = gamma;
+    unsigned char* base = nullptr;
+    IGR_TRY(noalloc_scratch(&base));
+    double* partial = reinterpret_cast<double*>(base + kNoAllocPartialOff);
+    double* result = reinterpret_cast<double*>(base + kNoAllocResultOff);
+    int* flag = reinterpret_cast<int*>(base + kNoAllocFlagOff);
+    hipStream_t s = as_stream(stream);
+    IGR_TRY(precision == IGR_F64   ? dt_noalloc_t<double>(g, U, partial, result, flag, cfl, s)
+            : precision == IGR_F32 ? dt_noalloc_t<float>(g, U, partial, result, flag, cfl, s)
+            : precision == IGR_F16_F32 ? dt_noalloc_t<f16>(g, U, partial, result, flag, cfl, s)
+                                       : dt_noalloc_t<bf16>(g, U, partial, result, flag, cfl, s));
+    int bad = 0;
+    IGR_HIP(hipMemcpyAsync(dt, result, sizeof(double), hipMemcpyDeviceToHost, s));
+    IGR_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    IGR_HIP(hipStreamSynchronize(s));
+    if (bad) return fail(IGR_ENONFINITE, "a kernel saw rho <= 0, p <= 0 or a non-finite value");
+    return IGR_OK;
+}
 
 }  // extern "C"

@@ -77,6 +77,8 @@ _SIGNATURES = {
     "igr_compute_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "igr_compute_dt_noalloc": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "igr_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "igr_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
