@@ -3,12 +3,19 @@
 A step is one SSP-RK3 step of the whole path (three right-hand sides, each
 with its ghost fill, Sigma source, Jacobi sweeps and fused reconstruction +
 LLF flux + divergence + stage update, plus the FP64 CFL reduction; the
-timed steps run through igr_advance, which in the FP32-arithmetic forms
-fuses each later step's CFL maximum into the previous step's last stage)
-over the
-256^3 periodic box (rho = 1 + 0.2 * Gaussian-smoothed noise, solenoidal
-k^-2 velocity at rms Mach 1.5, p = 1, alpha = dx^2, 5 sweeps, CFL 0.5),
-with the state resident in HBM.
+timed steps run through igr_advance with the CFL time step), with the state
+resident in HBM.
+
+Default workload: the largest single-GPU multi-jet box, 1024^3 cells, a
+4 x 4 array of Mach-3 inflow discs of radius 10 cells on the x-min face
+(rho = 0.5, p = 8, +-5 % seeded u_x), ambient (1, 0, 1), outflow elsewhere,
+10 Jacobi sweeps per stage, alpha = 4 dx^2 (alpha = dx^2 loses positivity at
+the Mach-3 jet edges under the unlimited fifth-order reconstruction).  The
+FP64 form is `value`; FP32 and the 16-bit storage forms are timed the same
+way under `forms`, each with its rate relative to FP64, the device bytes in
+use and its per-field relative L1 error against the FP64 run after the same
+number of fixed-dt steps.  The 256^3 periodic box (rms Mach 1.5,
+alpha = dx^2, 5 sweeps) is timed under `extra`.
 
 Prints one JSON line: cell-updates/s (cells x steps / time), the roofline
 of the dominant kernel measured with HIP events on the solver's stream
@@ -110,8 +117,22 @@ def load_traffic(kernel: str, workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds_target: float = 15.0):
-    """The FP64 oracle on a 128^3 instance of the same workload recipe."""
+def _oracle_rate(prob, U, sig, steps_max: int, seconds_target: float, dt_fn):
+    import torch  # noqa: F401
+
+    from oracle import igr_ref as ref
+
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        U, sig = ref.rk3_step(prob, U, sig, dt_fn(U))
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or steps >= steps_max:
+            return steps, el
+
+
+def cpu_baseline_box(w, seconds_target: float = 15.0):
+    """The FP64 oracle on a 128^3 instance of the periodic-box recipe."""
     import torch
 
     from oracle import igr_ref as ref
@@ -119,33 +140,47 @@ def cpu_baseline(w, seconds_target: float = 15.0):
 
     n = 128
     ws = inputs.periodic_box(n=n, seed=w.seed)
-    U = torch.from_numpy(ws.U)
     prob = ref.Problem(n, n, n, ws.dx, ws.dy, ws.dz, alpha=ws.alpha, faces=("periodic",) * 6, nsweeps=ws.nsweeps)
     sig = torch.zeros((n, n, n), dtype=torch.float64)
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        U, sig = ref.rk3_step(prob, U, sig, ref.compute_dt(prob, U, w.cfl))
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds_target or steps >= 50:
-            break
+    steps, el = _oracle_rate(prob, torch.from_numpy(ws.U), sig, 50, seconds_target,
+                             lambda V: ref.compute_dt(prob, V, w.cfl))
+    return {"value": n ** 3 * steps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} RK3 steps of the FP64 oracle on the 128^3 periodic box (same recipe and seed), "
+                      f"{el:.1f} s"}
+
+
+def cpu_baseline_jets(w, seconds_target: float = 15.0):
+    """The FP64 oracle on a 128^3 instance of the multi-jet recipe (the
+    same 4 x 4 discs of radius 10 cells, Mach 3, seed, alpha = 4 dx^2 and
+    10 sweeps), CFL time step, timed on the host cores."""
+    import torch
+
+    from oracle import igr_ref as ref
+    from paper_2505_07392_amd import inputs
+
+    n = 128
+    ws = jet_workload(n, 0, build_state=True)
+    patches = tuple(ref.Patch(j.yc, j.zc, j.r, j.rho, j.ux, j.uy, j.uz, j.p, j.width) for j in ws.jets)
+    prob = ref.Problem(n, n, n, ws.dx, ws.dy, ws.dz, gamma=ws.gamma, alpha=ws.alpha, faces=tuple(ws.faces),
+                       patches=patches, nsweeps=ws.nsweeps)
+    U = torch.from_numpy(ws.U)
+    sig = torch.zeros((n, n, n), dtype=torch.float64)
+    steps, el = _oracle_rate(prob, U, sig, 50, seconds_target, lambda V: ref.compute_dt(prob, V, ws.cfl))
     out = {"value": n ** 3 * steps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
            "kind": "oracle",
-           "sample": f"{steps} RK3 steps of the FP64 oracle on the 128^3 periodic box (same recipe and "
-                     f"seed as the 256^3 workload), {el:.1f} s"}
-    # the same oracle on one thread: one step from the initial state
+           "sample": f"{steps} RK3 steps of the FP64 oracle on a 128^3 instance of the multi-jet recipe "
+                     f"(4 x 4 Mach-3 discs of radius 10 cells, 10 sweeps, alpha = 4 dx^2), {el:.1f} s"}
     nthreads = torch.get_num_threads()
     torch.set_num_threads(1)
     try:
         U1 = torch.from_numpy(ws.U)
         sig1 = torch.zeros((n, n, n), dtype=torch.float64)
-        t0 = time.perf_counter()
-        ref.rk3_step(prob, U1, sig1, ref.compute_dt(prob, U1, w.cfl))
-        el1 = time.perf_counter() - t0
+        s1, el1 = _oracle_rate(prob, U1, sig1, 1, 0.0, lambda V: ref.compute_dt(prob, V, ws.cfl))
     finally:
         torch.set_num_threads(nthreads)
-    out["single_thread"] = {"value": n ** 3 / el1, "cores": 1,
-                            "sample": f"1 RK3 step of the same 128^3 box, {el1:.1f} s"}
+    out["single_thread"] = {"value": n ** 3 * s1 / el1, "cores": 1,
+                            "sample": f"1 RK3 step of the same 128^3 multi-jet box, {el1:.1f} s"}
     return out
 
 
@@ -173,106 +208,110 @@ def run_form(w, precision, steps, warmup, sigma_block=0, order=5, smoother="jaco
     return el, kt, sb
 
 
-def jet_workload(n: int, nsteps: int):
+def jet_workload(n: int, nsteps: int, build_state: bool = False):
     from paper_2505_07392_amd import inputs
 
     w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10, nsteps=nsteps,
-                         build_state=False)
+                         build_state=build_state)
     w.alpha = 4.0 * w.dx * w.dx     # Mach-3 jets need alpha = 4 dx^2 (alpha = dx^2 loses positivity)
     return w
 
 
-def study_jets(n: int, nsteps: int, forms, timed_steps: int, warmup: int):
-    """Multi-jet box: rate of each precision form, device memory in use, and
-    per-field rel L1 error (the six fields and the derived pressure) of the
-    other forms against the FP64 run after `nsteps` steps with the same
-    fixed dt (computed on the GPU)."""
+FIELD_NAMES = ["rho", "mx", "my", "mz", "E", "Sigma", "p"]
+
+
+def _final_fields(s, U, S, gamma):
+    """The six fields and the derived pressure as one FP64 device array,
+    formed in place (at 1024^3 each FP64 field is 8.6 GB)."""
+    import torch
+
+    nz, ny, nx = (d - 6 for d in U.shape[1:])
+    fin = torch.empty((7, nz, ny, nx), dtype=torch.float64, device=U.device)
+    fin[:5].copy_(s.interior(U))
+    fin[5].copy_(s.interior(S))
+    pr = fin[6]
+    torch.mul(fin[1], fin[1], out=pr)
+    pr.addcmul_(fin[2], fin[2]).addcmul_(fin[3], fin[3]).div_(fin[0]).mul_(-0.5).add_(fin[4])
+    pr.mul_(gamma - 1.0)
+    return fin
+
+
+def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None):
+    """Multi-jet box in each precision form (FP64 first): the rate over
+    `steps` CFL steps after `warmup` (igr_advance, HIP-event timing of every
+    launch), the device memory in use, and the per-field rel L1 error of the
+    six fields and the derived pressure against the FP64 run after
+    `err_steps` steps from the initial state with one fixed dt (0.8 x the
+    FP64 CFL step of the initial state)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
 
-    w = jet_workload(n, nsteps)
-    out = {"workload": f"multi_jet_{n}", "cells": w.cells, "steps": nsteps, "alpha_dx2": 4.0, "sweeps": w.nsweeps,
-           "forms": {}}
-    ref = None
-    dt = None
-    names = ["rho", "mx", "my", "mz", "E", "Sigma", "p"]
+    w = jet_workload(n, err_steps)
+    say = log or (lambda m: print(m, file=sys.stderr, flush=True))
+    out, ref, dt = {}, None, None
     for prec in forms:
-        print(f"[bench] multi-jet {n}^3 {prec}: building the state", file=sys.stderr, flush=True)
+        say(f"[bench] multi-jet {n}^3 {prec}: building the state")
         s = igr.Solver.from_workload(w, precision=prec)
         U = s.new_state()
         inputs.fill_multi_jet_state(w, s.interior(U))
-        U0 = U.clone() if nsteps > 0 else None
         S = s.new_field()
         if dt is None:
             dt = 0.8 * s.compute_dt(U, w.cfl)
-            out["dt"] = dt
-        free, total = torch.cuda.mem_get_info()
-        print(f"[bench] multi-jet {n}^3 {prec}: timing", file=sys.stderr, flush=True)
-        s.advance(U, S, warmup, dt_fixed=dt, sync=False)
+        say(f"[bench] multi-jet {n}^3 {prec}: {warmup} warm-up + {steps} timed steps")
+        s.advance(U, S, warmup, cfl=w.cfl, sync=False)
+        s.check()
         torch.cuda.synchronize()
+        free, total = torch.cuda.mem_get_info()
         s.timing(True)
         t0 = time.perf_counter()
-        s.advance(U, S, timed_steps, dt_fixed=dt, sync=False)
+        s.advance(U, S, steps, cfl=w.cfl, sync=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         s.timing(False)
         s.check()
         kt = {k: s.kernel_time(k) for k in igr.kernel_names()}
-        form = {"value": w.cells * timed_steps / el, "ms_per_step": 1e3 * el / timed_steps,
-                "device_bytes_in_use": total - free, "frac_of_288GB": (total - free) / 288e9}
-        form["sigma_block"] = s.sigma_block
+        form = {"value": w.cells * steps / el, "ms_per_step": 1e3 * el / steps, "elapsed_s": el,
+                "device_bytes_in_use": total - free, "frac_of_288GB": round((total - free) / 288e9, 4),
+                "sigma_block": s.sigma_block, "kernel_times": kt}
         form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block))
-        if nsteps > 0:
-            print(f"[bench] multi-jet {n}^3 {prec}: {nsteps}-step run", file=sys.stderr, flush=True)
-            U.copy_(U0)
-            del U0
+        if err_steps > 0:
+            say(f"[bench] multi-jet {n}^3 {prec}: {err_steps} fixed-dt steps for the error")
+            inputs.fill_multi_jet_state(w, s.interior(U))
             S.zero_()
             try:
-                for it in range(nsteps):
-                    s.step(U, S, dt_fixed=dt, sync=False)
-                    if it % 50 == 49:
-                        s.check()
-                        print(f"[bench]   step {it + 1}", file=sys.stderr, flush=True)
-                s.check()
+                s.advance(U, S, err_steps, dt_fixed=dt, sync=True)
             except igr.NonFiniteError as e:
-                form["run_failed"] = f"non-physical state reported by step {it + 1}: {e}"
-                out["forms"][prec] = form
-                s.close()
-                continue
-            # the six fields and the derived pressure, formed in place (at
-            # 1024^3 each FP64 field is 8.6 GB)
-            fin = torch.empty((7, w.nz, w.ny, w.nx), dtype=torch.float64, device=U.device)
-            fin[:5].copy_(s.interior(U))
-            fin[5].copy_(s.interior(S))
-            pr = fin[6]
-            torch.mul(fin[1], fin[1], out=pr)
-            pr.addcmul_(fin[2], fin[2]).addcmul_(fin[3], fin[3]).div_(fin[0]).mul_(-0.5).add_(fin[4])
-            pr.mul_(w.gamma - 1.0)
-            if prec == "f64":
-                ref = fin
-            elif ref is not None:
-                err = [float((fin[f] - ref[f]).abs().sum() / ref[f].abs().sum()) if float(ref[f].abs().sum()) > 0
-                       else 0.0 for f in range(len(names))]
-                form["rel_l1_vs_f64"] = dict(zip(names, err))
-            del fin
-        out["forms"][prec] = form
+                form["run_failed"] = f"non-physical state in the fixed-dt run: {e}"
+            else:
+                fin = _final_fields(s, U, S, w.gamma)
+                if prec == "f64":
+                    ref = fin
+                elif ref is not None:
+                    err = [float((fin[f] - ref[f]).abs().sum() / ref[f].abs().sum())
+                           if float(ref[f].abs().sum()) > 0 else 0.0 for f in range(len(FIELD_NAMES))]
+                    form["rel_l1_vs_f64"] = dict(zip(FIELD_NAMES, err))
+                    del fin
+        out[prec] = form
         del U, S
         s.close()
         torch.cuda.empty_cache()
-    print(json.dumps(out), flush=True)
+    return w, out, dt
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="multi_jet", choices=["multi_jet", "periodic_box"])
+    ap.add_argument("--n", type=int, default=None, help="cells per side (default 1024 multi-jet, 256 box)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--forms", default="f32,f16,bf16", help="extra precision forms timed on the same workload")
+    ap.add_argument("--err-steps", type=int, default=20,
+                    help="fixed-dt steps of the multi-jet error run per form (0: none)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 256^3 periodic box under `extra`")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--study", default=None, help="multi-jet study: 'jets:<n>:<steps>:<forms>'")
     ap.add_argument("--sigma-block", type=int, default=0, choices=[0, 1, 2],
                     help="Sigma pass structure: 1 single sweeps, 2 two-sweep passes (0: library default)")
     ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
@@ -304,18 +343,32 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 4,
                           "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
-    if args.study:
-        _, n, nst, forms = args.study.split(":")
-        study_jets(int(n), int(nst), forms.split(","), args.steps, args.warmup)
-        return
-    print(f"[bench] generating the {args.n}^3 periodic box", file=sys.stderr, flush=True)
-    w = inputs.periodic_box(n=args.n, seed=0)
-    print(f"[bench] timing {args.precision}: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)
-    cells = w.cells
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
     csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
+    forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
 
-    el, kt, sb = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
+    if args.workload == "multi_jet":
+        n = args.n or 1024
+        w, res, dt_err = jets_forms(n, [args.precision] + forms_req, args.steps, args.warmup, args.err_steps)
+        main_form = res.pop(args.precision)
+        cells, el, kt, sb = w.cells, main_form["elapsed_s"], main_form.pop("kernel_times"), main_form["sigma_block"]
+        workload = f"multi_jet_{n}"
+        desc = (f"{workload}: {n}^3 multi-jet box, 4 x 4 Mach-3 inflow discs of radius 10 cells on the x-min "
+                f"face (rho 0.5, p 8, +-5 % seeded u_x), ambient (1, 0, 1), outflow elsewhere, "
+                f"{w.nsweeps} Jacobi sweeps, alpha = 4 dx^2 (not dx^2: the Mach-3 jet edges lose positivity "
+                f"at alpha = dx^2), CFL 0.5")
+    else:
+        n = args.n or 256
+        print(f"[bench] generating the {n}^3 periodic box", file=sys.stderr, flush=True)
+        w = inputs.periodic_box(n=n, seed=0)
+        cells = w.cells
+        el, kt, sb = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order,
+                              args.smoother)
+        workload = f"periodic_box_{n}"
+        desc = (f"{workload}: periodic box {n}^3, rms Mach 1.5, alpha = dx^2, {w.nsweeps} Jacobi sweeps, "
+                f"CFL 0.5")
+        main_form = None
+
     value = cells * args.steps / el
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -326,7 +379,6 @@ def main():
                                             sb, args.smoother) * cells
     except KeyError:
         abytes = None
-    workload = f"periodic_box_{args.n}"
     achieved = abytes / avg_s / 1e9 if abytes else None
     traffic = load_traffic(dom, f"{workload}_{args.precision}") if (args.order == 5 and not args.sigma_block
                                                                       and args.smoother == "jacobi") else None
@@ -336,20 +388,26 @@ def main():
                 "algorithmic_bytes_per_launch": abytes}
     kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1], "avg_ms": round(v[0] / v[1], 5)}
                for k, v in kt.items() if v[1] > 0}
-
-    forms = {}
-    for f in [x for x in args.forms.split(",") if x and x != args.precision]:
-        print(f"[bench] timing {f}", file=sys.stderr, flush=True)
-        e2, kt2, sb2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
-        forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
-                    "vs_f64": None, "sigma_block": sb2}
-        forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, sb2, args.smoother))
-
-    if args.precision == "f64":
-        for f in forms:
-            forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
     kernels.update({k + "_roofline": v for k, v in kernel_rooflines(kt, cells, args.precision, w.nsweeps,
                                                                     sb, args.smoother).items()})
+
+    forms = {}
+    if args.workload == "multi_jet":
+        for f, d in res.items():
+            d.pop("kernel_times", None)
+            d.pop("elapsed_s", None)
+            d["vs_f64"] = round(d["value"] / value, 3) if args.precision == "f64" else None
+            forms[f] = d
+    else:
+        for f in forms_req:
+            print(f"[bench] timing {f}", file=sys.stderr, flush=True)
+            e2, kt2, sb2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
+            forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
+                        "vs_f64": None, "sigma_block": sb2}
+            forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, sb2, args.smoother))
+            if args.precision == "f64":
+                forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
+
     line = {
         "metric": "cell-updates/s per RK3 step (incl. Sigma Jacobi)",
         "value": value,
@@ -364,17 +422,38 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{workload} periodic box {args.n}^3, rms Mach 1.5, alpha=dx^2, "
-                               f"{w.nsweeps} Jacobi sweeps, CFL 0.5", "cells": cells,
-                   "sweeps": w.nsweeps, "precision": args.precision, "order": args.order,
-                   "smoother": args.smoother, "sigma_block": sb},
+        "config": {"workload": desc, "cells": cells, "sweeps": w.nsweeps, "alpha_over_dx2": w.alpha / w.dx ** 2,
+                   "precision": args.precision, "order": args.order, "smoother": args.smoother,
+                   "sigma_block": sb},
         "roofline": roofline,
         "kernels": kernels,
         "forms": forms,
     }
+    if main_form is not None:
+        line["device_bytes_in_use"] = main_form["device_bytes_in_use"]
+        line["frac_of_288GB"] = main_form["frac_of_288GB"]
+        line["error_run"] = {"steps": args.err_steps, "dt_fixed": dt_err,
+                             "reference": "the FP64 GPU run of the same steps (parity-tested against the oracle)"}
+    if args.workload == "multi_jet" and not args.no_extra:
+        print("[bench] extra: generating the 256^3 periodic box", file=sys.stderr, flush=True)
+        wb = inputs.periodic_box(n=256, seed=0)
+        extra = {}
+        for prec in ["f64"] + [f for f in forms_req if f != "f64"]:
+            print(f"[bench] extra: periodic box 256^3 {prec}", file=sys.stderr, flush=True)
+            eb, ktb, sbb = run_form(wb, prec, 20, 3)
+            extra[prec] = {"value": wb.cells * 20 / eb, "ms_per_step": 1e3 * eb / 20, "sigma_block": sbb}
+            extra[prec].update(kernel_rooflines(ktb, wb.cells, prec, wb.nsweeps, sbb))
+        for prec in extra:
+            extra[prec]["vs_f64"] = round(extra[prec]["value"] / extra["f64"]["value"], 3)
+        line["extra"] = {"periodic_box_256": {"workload": "periodic box 256^3, rms Mach 1.5, alpha = dx^2, "
+                                                          "5 Jacobi sweeps, CFL 0.5; 3 warm-up + 20 timed steps",
+                                              "forms": extra}}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w)
+        if args.workload == "multi_jet":
+            line["cpu_baseline"] = cpu_baseline_jets(w)
+        else:
+            line["cpu_baseline"] = cpu_baseline_box(w)
     print(json.dumps(line), flush=True)
 
 
