@@ -21,7 +21,9 @@ interior) are ever read; edge and corner ghosts are filled but unused.
 Method (paper section "Innovations Realized")
 ---------------------------------------------
 * IGR-modified Euler system, eqs. (6)-(8) with tau = 0: p is replaced by
-  p + Sigma in the momentum and energy fluxes.
+  p + Sigma in the momentum and energy fluxes.  With a nonzero shear or
+  bulk viscosity the viscous stress of eq. (5) enters as in eqs. (2)-(3)
+  and (7)-(8).
 * Entropic pressure, eq. (9):
   alpha [tr((grad u)^2) + tr^2(grad u)] = Sigma/rho - alpha div(grad Sigma / rho).
 * "Discretization" subsection: second-order central velocity gradients for
@@ -50,6 +52,13 @@ Readings where the paper is silent:
   the extrapolated state by a tanh profile in the distance to the disc
   centre (a sharp disc when the width is zero).
 * dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d.
+* Viscous terms: second-order central velocity gradients at cell centres
+  (the paper: second-order derivatives of u suffice), ghost gradients by
+  the rule of Sigma's ghosts, face gradients reconstructed with the weights
+  of the conserved variables (Algorithm 1 reconstructs the gradients with
+  the same coefficients), face velocities from the reconstructed conserved
+  variables, and the mean of the two sides' viscous fluxes (no dissipation
+  term); mu and zeta constant.
 
 Parity pins (tests/test_oracle_*.py): reconstruction polynomial exactness
 (degree <= 4 for the fifth-order, <= 2 for the third-order interpolant)
@@ -60,7 +69,10 @@ flux consistency F(U, U) = F(U); uniform-state preservation; axis
 permutation and mirror symmetry; alpha = 0 against an independently written
 per-cell Lax-Friedrichs code; Sod against the exact Riemann solution;
 periodic conservation; fifth- and third-order convergence on an entropy
-wave; RK3 against its stability polynomial.
+wave; RK3 against its stability polynomial; the viscous stress and flux
+against linear velocity fields (closed-form stress and heating, zero for a
+rigid rotation), the Fourier symbol of the viscous operator on a shear
+wave, and discrete conservation with viscosity.
 """
 
 from __future__ import annotations
@@ -131,6 +143,8 @@ class Problem:
     nsweeps: int = 5
     order: int = 5          # reconstruction order: 5 or 3 ("Discretization")
     smoother: str = "jacobi"   # Sigma sweeps: "jacobi" or "rbgs" (red-black Gauss-Seidel)
+    mu: float = 0.0         # shear viscosity, eq. (5) (0: the Euler system)
+    zeta: float = 0.0       # bulk viscosity, eq. (5)
 
     @property
     def shape(self):
@@ -418,14 +432,79 @@ def flux_divergence(prob: Problem, Upad: torch.Tensor, Spad: torch.Tensor) -> to
     return L
 
 
+# ---------------------------------------------------------------------------
+# Viscous stress (eqs. (1)-(3) with eq. (5); "Discretization"; Algorithm 1's
+# viscous flux)
+# ---------------------------------------------------------------------------
+
+def velocity_gradient(prob: Problem, Upad: torch.Tensor, g: int = G) -> torch.Tensor:
+    """G[i][j] = d u_i / d x_j at interior cells by second-order central
+    differences of u = m / rho.  Returns [3, 3, nz, ny, nx]."""
+    u = Upad[1:4] / Upad[0]
+    rows = []
+    for i in range(3):
+        rows.append(torch.stack([(_interior(prob, u[i], g, j, +1) - _interior(prob, u[i], g, j, -1)) /
+                                 (2.0 * prob.h(j)) for j in range(3)]))
+    return torch.stack(rows)
+
+
+def pad_gradient(prob: Problem, Gm: torch.Tensor, g: int = G) -> torch.Tensor:
+    """Gradient with g ghost layers, per component: periodic wrap, else a
+    copy of the first interior cell (every non-periodic face, inflow discs
+    included), the ghost rule of Sigma."""
+    return torch.stack([torch.stack([pad_sigma(prob, Gm[i][j], g) for j in range(3)]) for i in range(3)])
+
+
+def viscous_stress(prob: Problem, Gm):
+    """Eq. (5): tau_ij = mu (G_ij + G_ji) + (zeta - 2 mu / 3) delta_ij div u,
+    G_ij = d u_i / d x_j.  Returns a 3 x 3 nested list of tensors."""
+    div = Gm[0][0] + Gm[1][1] + Gm[2][2]
+    tau = [[prob.mu * (Gm[i][j] + Gm[j][i]) for j in range(3)] for i in range(3)]
+    for i in range(3):
+        tau[i][i] = tau[i][i] + (prob.zeta - 2.0 * prob.mu / 3.0) * div
+    return tau
+
+
+def viscous_flux_divergence(prob: Problem, Upad: torch.Tensor, Gpad: torch.Tensor) -> torch.Tensor:
+    """Viscous part of L(U).  At every face along axis d: the velocity
+    gradient on each side reconstructed from the cell-centre gradients with
+    the weights of the conserved variables, the face velocity on each side
+    from the reconstructed conserved variables, the stress of each side, and
+    the mean of the two sides' viscous fluxes: -tau e_d for the momenta and
+    -(u . tau) e_d for the energy (eqs. (2)-(3)); none for the mass.
+    L_v = - sum_d (F_{i+1/2} - F_{i-1/2}) / h_d."""
+    L = torch.zeros((5,) + prob.shape, dtype=Upad.dtype)
+    for d in range(3):
+        UL, UR = reconstruct(prob, Upad, d)
+        GL = [[None] * 3 for _ in range(3)]
+        GR = [[None] * 3 for _ in range(3)]
+        for i in range(3):
+            for j in range(3):
+                GL[i][j], GR[i][j] = reconstruct(prob, Gpad[i][j], d)
+        tL, tR = viscous_stress(prob, GL), viscous_stress(prob, GR)
+        uL, uR = UL[1:4] / UL[0], UR[1:4] / UR[0]
+        F = [torch.zeros_like(UL[0])]
+        for k in range(3):
+            F.append(-0.5 * (tL[k][d] + tR[k][d]))
+        F.append(-0.5 * (sum(uL[k] * tL[k][d] for k in range(3)) + sum(uR[k] * tR[k][d] for k in range(3))))
+        F = torch.stack(F)
+        n = prob.n(d)
+        dim = -1 - d
+        L = L - (F.narrow(dim, 1, n) - F.narrow(dim, 0, n)) / prob.h(d)
+    return L
+
+
 def rhs(prob: Problem, U: torch.Tensor, sigma0: torch.Tensor):
     """One right-hand-side evaluation: ghosts, Sigma solve warm-started from
-    sigma0, Sigma ghosts, reconstruction, LLF flux, divergence.
+    sigma0, Sigma ghosts, reconstruction, LLF flux, divergence, and with a
+    nonzero viscosity the viscous flux divergence.
 
     Returns (L(U), sigma)."""
     Upad = pad_state(prob, U)
     sig, _ = sigma_solve(prob, U, sigma0, Upad=Upad)
     L = flux_divergence(prob, Upad, pad_sigma(prob, sig, G))
+    if prob.mu != 0.0 or prob.zeta != 0.0:
+        L = L + viscous_flux_divergence(prob, Upad, pad_gradient(prob, velocity_gradient(prob, Upad)))
     return L, sig
 
 
