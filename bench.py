@@ -58,24 +58,45 @@ def sigma_schedule(nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
     return 1, pairs, later - 2 * pairs
 
 
-def algorithmic_bytes_per_cell(kernel: str, esize: int, csize: int, nsweeps: int, sigma_block: int = 2,
+# bytes per stored value of each form: (state U^n, RK stage buffer, Sigma,
+# arithmetic type of the source b and of a stored 1/rho)
+FORM_BYTES = {"f64": (8, 8, 8, 8), "f32": (4, 4, 4, 4), "f16": (2, 2, 2, 4), "bf16": (2, 2, 2, 4),
+              "bf16d": (4, 2, 2, 4)}
+
+
+def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_block: int = 2,
                                smoother: str = "jacobi") -> float:
     """Compulsory HBM bytes per interior cell for one launch of `kernel`
-    (averaged over the launches of one right-hand side)."""
+    (averaged over the launches of one RK step).  The split form (bf16d)
+    reads a later stage state as U^n (FP32) plus its BF16 difference,
+    writes the differences of stages 1 and 2 and U^(n+1) (FP32) in stage 3,
+    and its first Sigma pass stores 1/rho (FP32), which the later passes
+    read instead of rho."""
+    eu, ed, es, c = FORM_BYTES[precision]
+    split = precision == "bf16d"
     if kernel == "flux_rk":
+        if split:
+            # stage 1: U^n, Sigma -> delta1; 2: U^n + delta1, Sigma -> delta2;
+            # 3: U^n + delta2, Sigma -> U^(n+1)
+            return (5 * eu + es + 5 * ed + 5 * (eu + ed) + es + 5 * ed + 5 * (eu + ed) + es + 5 * eu) / 3.0
         # stage 1 reads U (5) + Sigma (1), writes 5; stages 2 and 3 also read Un (5)
-        return esize * (11 + 16 + 16) / 3.0
+        return eu * (11 + 16 + 16) / 3.0
     if kernel == "jacobi":
         # first pass (one or two sweeps): reads rho, m, Sigma; writes Sigma,
         # b.  Later passes, single or two sweeps: read Sigma, rho, b; write Sigma
         nf, npair, nsingle = sigma_schedule(nsweeps, sigma_block, smoother)
-        first = 5 * esize + esize + csize
-        later = 3 * esize + csize
+        if split:
+            state = 4 * (eu + ed * 2.0 / 3.0)      # rho, m: stage 1 from U^n, stages 2, 3 from U^n + delta
+            first = state + 2 * es + c + c          # + Sigma in/out, b and 1/rho written
+            later = 2 * es + c + c                  # Sigma in/out, 1/rho and b read
+        else:
+            first = 5 * eu + eu + c
+            later = 3 * eu + c
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":
-        return 4 * esize + csize          # rho, m read; b written
+        return 4 * eu + c          # rho, m read; b written
     if kernel == "dt":
-        return 5 * esize
+        return 5 * eu
     raise KeyError(kernel)
 
 
@@ -83,13 +104,11 @@ def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: 
     """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
     Sigma kernels from their measured average launch time (sigma_block: the
     pass structure the context ran)."""
-    esz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
-    csz = 8 if precision == "f64" else 4
     out = {}
     for k in ("flux_rk", "jacobi"):
         ms, cnt = kt[k]
         if cnt:
-            ab = algorithmic_bytes_per_cell(k, esz, csz, nsweeps, sigma_block, smoother) * cells
+            ab = algorithmic_bytes_per_cell(k, precision, nsweeps, sigma_block, smoother) * cells
             gbs = ab / (ms / cnt / 1e3) / 1e9
             out[k] = {"avg_ms": round(ms / cnt, 5), "launches": cnt, "achieved_GBs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -306,8 +325,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="multi_jet", choices=["multi_jet", "periodic_box"])
     ap.add_argument("--n", type=int, default=None, help="cells per side (default 1024 multi-jet, 256 box)")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f16", "bf16"])
-    ap.add_argument("--forms", default="f32,f16,bf16", help="extra precision forms timed on the same workload")
+    ap.add_argument("--precision", default="f64", choices=sorted(FORM_BYTES))
+    ap.add_argument("--forms", default="f32,bf16d,f16,bf16", help="extra precision forms timed on the same workload")
     ap.add_argument("--err-steps", type=int, default=20,
                     help="fixed-dt steps of the multi-jet error run per form (0: none)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 256^3 periodic box under `extra`")
@@ -343,8 +362,6 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 4,
                           "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
-    esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-    csize = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
     forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
 
     if args.workload == "multi_jet":
@@ -375,8 +392,7 @@ def main():
     ms, count = kt[dom]
     avg_s = ms / count / 1e3
     try:
-        abytes = algorithmic_bytes_per_cell(dom, esize[args.precision], csize[args.precision], w.nsweeps,
-                                            sb, args.smoother) * cells
+        abytes = algorithmic_bytes_per_cell(dom, args.precision, w.nsweeps, sb, args.smoother) * cells
     except KeyError:
         abytes = None
     achieved = abytes / avg_s / 1e9 if abytes else None

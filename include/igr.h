@@ -75,7 +75,7 @@ enum {
 
 enum { IGR_BC_PERIODIC = 0, IGR_BC_EXTRAP = 1 };
 
-enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2, IGR_F16_F32 = 3 };
+enum { IGR_F64 = 0, IGR_F32 = 1, IGR_BF16_F32 = 2, IGR_F16_F32 = 3, IGR_F32_BF16D = 4 };
 
 enum { IGR_SMOOTH_JACOBI = 0, IGR_SMOOTH_RBGS = 1 };
 
@@ -138,6 +138,8 @@ typedef struct {
     int32_t nsweeps;
     int32_t sigma_block;
     int32_t smoother;
+    double mu;     /* shear viscosity of eq. (5), >= 0 (0: the Euler system) */
+    double zeta;   /* bulk viscosity of eq. (5), >= 0 */
 } igr_opts;
 
 typedef struct igr_ctx igr_ctx;

@@ -15,6 +15,7 @@
 #include "igr_sigma.h"
 #include "igr_adjoint.h"
 #include "igr_kernels.h"
+#include "igr_viscous.h"
 
 using namespace igr;
 
@@ -41,9 +42,11 @@ int fail(int code, const std::string& msg) {
         if (rc_ != IGR_OK) return rc_; \
     } while (0)
 
-enum KernelId { K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_SWEEP, K_ADJOINT, K_COUNT };
-const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source", "jacobi", "flux_rk",
-                                           "dt",       "sums",     "resid",  "sweep",  "adjoint"};
+enum KernelId {
+    K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_SWEEP, K_ADJOINT, K_VISCOUS, K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source",  "jacobi", "flux_rk", "dt",
+                                           "sums",     "resid",    "sweep",   "adjoint", "viscous"};
 
 struct TimingRecord {
     int kernel;
@@ -60,11 +63,15 @@ struct igr_ctx {
     int nsweeps = 5;
     int order = 5;         // reconstruction order (5 or 3)
     int smoother = IGR_SMOOTH_JACOBI;
+    double mu = 0.0, zeta = 0.0;   // shear and bulk viscosity (eq. (5))
+    bool viscous = false;          // mu or zeta nonzero
     int sigma_block = 1;   // Sigma pass structure (1: single sweeps, 2: first + two-sweep passes, 3..5: fused march)
     int faces[6] = {0, 0, 0, 0, 0, 0};
     int device = 0;
-    size_t esize = 8;     // storage bytes per element
-    size_t csize = 8;     // arithmetic bytes per element (source array)
+    size_t esize = 8;     // storage bytes per element of a state (U^n, rhs)
+    size_t dsize = 8;     // storage bytes per element of an RK stage buffer
+    size_t ssize = 8;     // storage bytes per element of Sigma
+    size_t csize = 8;     // arithmetic bytes per element (source array, stored 1/rho)
     std::vector<igr_patch> patches;
     std::vector<int> h_owner;     // per x-min column (k*ny + j): nearest disc or -1
     int* d_owner = nullptr;
@@ -74,7 +81,10 @@ struct igr_ctx {
     void* d_Ub = nullptr;
     void* d_sig2 = nullptr;
     void* d_b = nullptr;
-    void* d_ir = nullptr;         // 1/rho written by the first sweep (FP64)
+    void* d_ir = nullptr;         // 1/rho written by the first sweep (FP64, split form)
+    void* d_Unb = nullptr;        // split form: the other FP32 state of the U^n / U^(n+1) ping-pong
+    double* d_jet0 = nullptr;     // split form: zero jet states (ghosts of the stage differences)
+    void* d_G = nullptr;          // viscous: the 9 velocity-gradient components (arithmetic type)
     double* d_partial = nullptr;
     double* d_scalars = nullptr;  // [0] dt, [1..5] sums, [6] residual
     double* d_speed = nullptr;    // per-flux-block CFL maxima left by a step's last stage
@@ -160,13 +170,18 @@ int collect_timing(igr_ctx* c) {
 dim3 cell_block() { return dim3(64, 4, 1); }
 dim3 cell_grid(const Geom& g) { return dim3((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]); }
 
+// delta: U holds a split-form stage difference from U^n, whose ghost cells
+// were filled already: an inflow ghost of the stage state is
+// chi U_jet + (1 - chi)(U^n_ext + delta_ext), so its difference is
+// (1 - chi) delta_ext, the same blend with a zero jet state.
 template <class T>
-int fill_state_ghosts(igr_ctx* c, T* U, hipStream_t s) {
+int fill_state_ghosts(igr_ctx* c, T* U, hipStream_t s, bool delta = false) {
     const long long tot = bc_face_threads(c->g);
     if (tot / 256 + 1 > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the ghost fill");
     const int blocks = int((tot + 255) / 256);
     const int* owner = c->patches.empty() ? nullptr : c->d_owner;
-    IGR_TRY(launch(c, K_BC_STATE, s, [&] { k_bc_state<T><<<blocks, 256, 0, s>>>(U, c->g, owner, c->d_chi, c->d_jet); }));
+    const double* jet = delta ? c->d_jet0 : c->d_jet;
+    IGR_TRY(launch(c, K_BC_STATE, s, [&] { k_bc_state<T><<<blocks, 256, 0, s>>>(U, c->g, owner, c->d_chi, jet); }));
     return IGR_OK;
 }
 
@@ -248,9 +263,10 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 #ifndef IGR_PAIR_ZC_MIN
 #define IGR_PAIR_ZC_MIN 8
 #endif
-template <class T, bool FIRST>
-int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
-    using C = typename Storage<T>::C;
+template <class F, bool FIRST, bool HASD>
+int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* Sin,
+              typename F::TS* Sout, hipStream_t s) {
+    using C = typename F::C;
     const Geom& g = c->g;
     constexpr int NR = FIRST ? PAIR_NR_FIRST : PAIR_NR;
     const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + NR - 3) / (NR - 2);
@@ -264,8 +280,8 @@ int pair_pass(igr_ctx* c, const T* U, const T* Sin, T* Sout, hipStream_t s) {
     C* b = static_cast<C*>(c->d_b);
     C* ir = static_cast<C*>(c->d_ir);
     return launch(c, K_JACOBI, s, [&] {
-        k_sweep_pair<T, NR, FIRST><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(U, Sin, Sout, b, ir, g,
-                                                                                      int(zc), tiles_x, tiles_y);
+        k_sweep_pair<F, NR, FIRST, HASD><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(
+            U, D, Sin, Sout, b, ir, g, int(zc), tiles_x, tiles_y);
     });
 }
 
@@ -307,16 +323,19 @@ long long sweep_speed_slots(const Geom& g) { return sweep_shape(g, SWEEP_RY_FIRS
 
 // speed (FP64 contexts, nullable): if the solve starts with a single first
 // sweep, that sweep also leaves the CFL maxima of U there and *nspeed is
-// their count; otherwise *nspeed is 0.
-template <class T>
-int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, hipStream_t s,
+// their count; otherwise *nspeed is 0.  The state swept from is U (+ D
+// with HASD: a split-form stage difference).
+template <class F, bool HASD = false>
+int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, typename F::TS* in,
+                    typename F::TS* other, int nsweeps, typename F::TS** result, hipStream_t s,
                     double* speed = nullptr, int* nspeed = nullptr) {
-    using C = typename Storage<T>::C;
+    using C = typename F::C;
+    using TS = typename F::TS;
     if (nspeed) *nspeed = 0;
-    T* src = in;
-    T* dst = other;
+    TS* src = in;
+    TS* dst = other;
     auto swap = [&] {
-        T* tmp = src;
+        TS* tmp = src;
         src = dst;
         dst = tmp;
     };
@@ -328,22 +347,23 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         C* b = static_cast<C*>(c->d_b);
         C* ir = static_cast<C*>(c->d_ir);
         auto single = [&](bool first, int colour = -1) {
-            T* out = colour < 0 ? dst : src;   // red-black half-sweeps work in place
-            constexpr bool SPD_OK = sizeof(C) == 8;   // CFL maxima formed in the first sweep: FP64
+            TS* out = colour < 0 ? dst : src;   // red-black half-sweeps work in place
+            constexpr bool SPD_OK = sizeof(C) == 8 && !HASD;   // CFL maxima formed in the first sweep: FP64
             const bool spd = SPD_OK && first && speed != nullptr;
             if (spd && nspeed) *nspeed = int(sf.blocks * SWEEP_RY_FIRST);
             return launch(c, K_JACOBI, s, [&] {
                 if (first && spd) {
                     if constexpr (SPD_OK)
-                        k_sweep_z<T, true, SWEEP_RY_FIRST, true>
+                        k_sweep_z<F, true, SWEEP_RY_FIRST, true>
                             <<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
-                                U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, speed, c->d_flag);
+                                U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, speed, c->d_flag);
                 } else if (first) {
-                    k_sweep_z<T, true, SWEEP_RY_FIRST><<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
-                        U, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, nullptr, nullptr);
+                    k_sweep_z<F, true, SWEEP_RY_FIRST, false, HASD>
+                        <<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
+                            U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, nullptr, nullptr);
                 } else {
-                    k_sweep_z<T, false, SWEEP_RY><<<dim3(unsigned(sl.blocks)), dim3(64, SWEEP_RY), 0, s>>>(
-                        U, src, out, b, ir, g, sl.zc, sl.tiles_x, sl.tiles_y, colour, nullptr, nullptr);
+                    k_sweep_z<F, false, SWEEP_RY, false, HASD><<<dim3(unsigned(sl.blocks)), dim3(64, SWEEP_RY), 0, s>>>(
+                        U, D, src, out, b, ir, g, sl.zc, sl.tiles_x, sl.tiles_y, colour, nullptr, nullptr);
                 }
             });
         };
@@ -365,7 +385,7 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             // forms the source, then pairs (an odd count keeps the single
             // first sweep, then pairs: measured faster than first pass +
             // pairs + a single sweep)
-            IGR_TRY((pair_pass<T, true>(c, U, src, dst, s)));
+            IGR_TRY((pair_pass<F, true, HASD>(c, U, D, src, dst, s)));
             swap();
             left -= 2;
         } else if (left > 0) {
@@ -375,7 +395,7 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
         }
         if (c->sigma_block == 2) {
             for (; left >= 2; left -= 2) {
-                IGR_TRY((pair_pass<T, false>(c, U, src, dst, s)));
+                IGR_TRY((pair_pass<F, false, HASD>(c, U, D, src, dst, s)));
                 swap();
             }
         }
@@ -383,7 +403,9 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             IGR_TRY(single(false));
             swap();
         }
-    } else {
+    } else if constexpr (!F::SPLIT) {
+        // the fused march reads one storage type (igr_init rejects it for the split form)
+        using T = typename F::TB;
         const int kmax = c->sigma_block < SigShape<T>::KMAX ? c->sigma_block : SigShape<T>::KMAX;
         int left = nsweeps;
         while (left > 0) {
@@ -392,17 +414,21 @@ int sigma_solve_buf(igr_ctx* c, T* U, T* in, T* other, int nsweeps, T** result, 
             left -= k;
             swap();
         }
+    } else {
+        return fail(IGR_EUNSUPPORTED, "the fused Sigma march needs a plain storage form");
     }
     *result = src;
     return fill_sigma_ghosts(c, src, s);
 }
 
-// As sigma_solve_buf, with the result always in `sig`.
-template <class T>
-int sigma_solve_impl(igr_ctx* c, T* U, T* sig, int nsweeps, hipStream_t s) {
-    T* res = nullptr;
-    IGR_TRY(sigma_solve_buf(c, U, sig, static_cast<T*>(c->d_sig2), nsweeps, &res, s));
-    if (res != sig) IGR_HIP(hipMemcpyAsync(sig, res, field_bytes(c, sizeof(T)), hipMemcpyDeviceToDevice, s));
+// As sigma_solve_buf from a state U of the step's type, with the result
+// always in `sig`.
+template <class F>
+int sigma_solve_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, int nsweeps, hipStream_t s) {
+    using TS = typename F::TS;
+    TS* res = nullptr;
+    IGR_TRY(sigma_solve_buf<F>(c, U, nullptr, sig, static_cast<TS*>(c->d_sig2), nsweeps, &res, s));
+    if (res != sig) IGR_HIP(hipMemcpyAsync(sig, res, field_bytes(c, sizeof(TS)), hipMemcpyDeviceToDevice, s));
     return IGR_OK;
 }
 
@@ -447,6 +473,23 @@ struct FluxShape<double> {
     static constexpr int BLOCKS = IGR_FLUX_BLOCKS_F64;
 };
 
+// The split form's stages 2 and 3 read each value as a base and a
+// difference, which needs more registers than the other FP32-arithmetic
+// forms: its own tile height and block target.
+#ifndef IGR_FLUX_TY_SPLIT
+#define IGR_FLUX_TY_SPLIT 11
+#endif
+#ifndef IGR_FLUX_BLOCKS_SPLIT
+#define IGR_FLUX_BLOCKS_SPLIT 768
+#endif
+template <class F>
+struct FluxShapeOf : FluxShape<typename F::C> {};
+template <>
+struct FluxShapeOf<Split> {
+    static constexpr int TY = IGR_FLUX_TY_SPLIT;
+    static constexpr int BLOCKS = IGR_FLUX_BLOCKS_SPLIT;
+};
+
 struct FluxLaunch {
     int tiles_x, tiles_y, zc, chunks;
     long long blocks() const { return (long long)tiles_x * tiles_y * chunks; }
@@ -467,26 +510,56 @@ FluxLaunch flux_launch(const Geom& g, int ty, int target_blocks) {
     return L;
 }
 
-template <class T, int MODE>
-int flux_impl(igr_ctx* c, const T* U, const T* sig, const T* Un, T* out, const double* dtp, double dt_fixed,
-              hipStream_t s, double* speed = nullptr, T* sig_out = nullptr) {
-    constexpr int TY = FluxShape<T>::TY;
-    const FluxLaunch L = flux_launch(c->g, TY, FluxShape<T>::BLOCKS);
+// The flux launch of storage form F (its shape follows the arithmetic type).
+template <class F, int MODE, bool HASD = false>
+int flux_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* sig,
+              const typename F::TB* Un, FluxOut<F, MODE>* out, const double* dtp, double dt_fixed, hipStream_t s,
+              double* speed = nullptr, typename F::TS* sig_out = nullptr) {
+    using Sh = FluxShapeOf<F>;
+    constexpr int TY = Sh::TY;
+    const FluxLaunch L = flux_launch(c->g, TY, Sh::BLOCKS);
     if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the flux launch");
     return launch(c, K_FLUX, s, [&] {
         if (c->order == 3)
-            k_flux_tiled<T, MODE, TY, 3><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
+            k_flux_tiled<F, MODE, TY, 3, HASD><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
+                U, D, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
         else
-            k_flux_tiled<T, MODE, TY, 5><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
-                U, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
+            k_flux_tiled<F, MODE, TY, 5, HASD><<<dim3(unsigned(L.blocks())), dim3(FLUX_TX, TY + 1), 0, s>>>(
+                U, D, sig, Un, out, dtp, dt_fixed, c->g, c->d_flag, L.tiles_x, L.tiles_y, L.zc, speed, sig_out);
     });
 }
 
-// blocks of one flux launch (the length of the fused CFL maxima)
-template <class T>
+// blocks of one flux launch of form F (the length of the fused CFL maxima)
+template <class F>
 long long flux_blocks(const igr_ctx* c) {
-    return flux_launch(c->g, FluxShape<T>::TY, FluxShape<T>::BLOCKS).blocks();
+    return flux_launch(c->g, FluxShapeOf<F>::TY, FluxShapeOf<F>::BLOCKS).blocks();
+}
+
+// Viscous terms added to `out` (the right-hand side, or the stage the
+// flux kernel just wrote) from the stage input U (+ D): velocity gradients,
+// their ghosts, then the viscous flux divergence.  IGR_F64 and IGR_F32.
+template <class F, int MODE, bool HASD = false>
+int viscous_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, FluxOut<F, MODE>* out,
+                 const double* dtp, double dt_fixed, hipStream_t s) {
+    if constexpr (F::SPLIT || sizeof(typename F::TB) < 4) {
+        return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
+    } else {
+        using C = typename F::C;
+        C* Gm = static_cast<C*>(c->d_G);
+        const Geom& g = c->g;
+        IGR_TRY(launch(c, K_VISCOUS, s, [&] {
+            k_vel_grad<F, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, g);
+        }));
+        for (int q = 0; q < 9; ++q) IGR_TRY(fill_sigma_ghosts(c, Gm + (size_t)q * g.fs, s));
+        return launch(c, K_VISCOUS, s, [&] {
+            if (c->order == 3)
+                k_viscous<F, MODE, 3, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, out, dtp, dt_fixed, g,
+                                                                                 c->mu, c->zeta);
+            else
+                k_viscous<F, MODE, 5, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, out, dtp, dt_fixed, g,
+                                                                                 c->mu, c->zeta);
+        });
+    }
 }
 
 template <class T>
@@ -510,36 +583,47 @@ int read_flag(igr_ctx* c, hipStream_t s) {
     return IGR_OK;
 }
 
-template <class T>
-int rhs_impl(igr_ctx* c, T* U, T* sig, T* rhs, hipStream_t s) {
+template <class F>
+int rhs_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, typename F::TB* rhs, hipStream_t s) {
     IGR_TRY(fill_state_ghosts(c, U, s));
-    IGR_TRY(sigma_solve_impl(c, U, sig, c->nsweeps, s));
-    return flux_impl<T, MODE_RHS>(c, U, sig, nullptr, rhs, nullptr, 0.0, s);
+    IGR_TRY(sigma_solve_impl<F>(c, U, sig, c->nsweeps, s));
+    IGR_TRY((flux_impl<F, MODE_RHS>(c, U, nullptr, sig, nullptr, rhs, nullptr, 0.0, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_RHS>(c, U, nullptr, rhs, nullptr, 0.0, s)));
+    return IGR_OK;
 }
 
-// The three RK stages of one step with the time step at *dtp (device) or
-// dt_fixed; with `speed` the last stage also leaves the per-block CFL
-// maxima of the new state there (one value per flux block).
-template <class T>
-// With cfl_dt the time step is the CFL step of U, formed in stage 1
-// (dtp is then ignored).
-int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hipStream_t s, double* speed,
-                bool cfl_dt = false, double cfl = 0.0) {
-    T* Ua = static_cast<T*>(c->d_Ua);
-    T* Ub = static_cast<T*>(c->d_Ub);
+// The three RK stages of one step from the state U (sigma: the previous
+// stage's Sigma, in and out) with the time step at *dtp (device) or
+// dt_fixed; with cfl_dt the time step is the CFL step of U, formed in stage
+// 1 (dtp is then ignored).  With `speed` the last stage also leaves the
+// per-block CFL maxima of the new state there (one value per flux block).
+// The new state goes to Unew: the plain forms write it in place (Unew ==
+// U); the split form writes it to the other FP32 state, because its last
+// stage still reads U^n around every cell it writes.
+template <class F>
+int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F::TS* sig, const double* dtp,
+                double dt_fixed, hipStream_t s, double* speed, bool cfl_dt = false, double cfl = 0.0) {
+    using TD = typename F::TD;
+    using TS = typename F::TS;
+    TD* Ua = static_cast<TD*>(c->d_Ua);
+    TD* Ub = static_cast<TD*>(c->d_Ub);
     // Sigma ping-pongs between the caller's buffer and the scratch copy
     // across the three stages; one copy at the end if it ends in scratch
-    T* cur = sig;
-    T* oth = static_cast<T*>(c->d_sig2);
-    auto solve = [&](T* Us, double* spd = nullptr, int* nspd = nullptr) -> int {
-        T* res = nullptr;
-        IGR_TRY(sigma_solve_buf(c, Us, cur, oth, c->nsweeps, &res, s, spd, nspd));
+    TS* cur = sig;
+    TS* oth = static_cast<TS*>(c->d_sig2);
+    auto solve = [&](auto hasd, const typename F::TB* Us, const TD* Ds, double* spd = nullptr,
+                     int* nspd = nullptr) -> int {
+        TS* res = nullptr;
+        IGR_TRY((sigma_solve_buf<F, decltype(hasd)::value>(c, Us, Ds, cur, oth, c->nsweeps, &res, s, spd, nspd)));
         if (res != cur) {
             oth = cur;
             cur = res;
         }
         return IGR_OK;
     };
+    using NoD = std::false_type;
+    // the later stages read U^n + difference in the split form
+    using LaterD = std::integral_constant<bool, F::SPLIT>;
     // stage 1: U1 = Un + dt L(Un)
     IGR_TRY(fill_state_ghosts(c, U, s));
     if (cfl_dt) {
@@ -547,56 +631,101 @@ int step_stages(igr_ctx* c, T* U, T* sig, const double* dtp, double dt_fixed, hi
         // when it can (FP64, solve starting with a single sweep), else the
         // standalone reduction runs; either way before the flux needs dt
         int nspd = 0;
-        IGR_TRY(solve(U, c->d_speed, &nspd));
+        IGR_TRY(solve(NoD{}, U, nullptr, c->d_speed, &nspd));
         if (nspd > 0)
             IGR_TRY(launch(c, K_DT, s, [&] {
                 k_dt_final<<<1, RED_THREADS, 0, s>>>(c->d_speed, nspd, cfl, c->d_scalars);
             }));
         else
-            IGR_TRY(speed_dt_impl(c, U, cfl, s));
+            IGR_TRY(speed_dt_impl(c, (const typename F::TB*)U, cfl, s));
         dtp = c->d_scalars;
     } else {
-        IGR_TRY(solve(U));
+        IGR_TRY(solve(NoD{}, U, nullptr));
     }
-    IGR_TRY((flux_impl<T, MODE_STAGE1>(c, U, cur, nullptr, Ua, dtp, dt_fixed, s)));
-    // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
-    IGR_TRY(fill_state_ghosts(c, Ua, s));
-    IGR_TRY(solve(Ua));
-    IGR_TRY((flux_impl<T, MODE_STAGE2>(c, Ua, cur, U, Ub, dtp, dt_fixed, s)));
-    // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
-    // solve ended in the scratch copy the kernel also writes Sigma's interior
-    // into the caller's buffer (its ghosts are scratch)
-    IGR_TRY(fill_state_ghosts(c, Ub, s));
-    IGR_TRY(solve(Ub));
-    IGR_TRY((flux_impl<T, MODE_STAGE3>(c, Ub, cur, U, U, dtp, dt_fixed, s, speed, cur != sig ? sig : nullptr)));
+    IGR_TRY((flux_impl<F, MODE_STAGE1>(c, U, nullptr, cur, nullptr, Ua, dtp, dt_fixed, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, nullptr, Ua, dtp, dt_fixed, s)));
+    if constexpr (F::SPLIT) {
+        // stage 2: U2 - Un = 1/4 ((U1 - Un) + dt L(U1)), U1 = Un + Ua
+        IGR_TRY(fill_state_ghosts(c, Ua, s, true));
+        IGR_TRY(solve(LaterD{}, U, Ua));
+        IGR_TRY((flux_impl<F, MODE_STAGE2, true>(c, U, Ua, cur, nullptr, Ub, dtp, dt_fixed, s)));
+        // stage 3: Un+1 = Un + 2/3 ((U2 - Un) + dt L(U2)), U2 = Un + Ub
+        IGR_TRY(fill_state_ghosts(c, Ub, s, true));
+        IGR_TRY(solve(LaterD{}, U, Ub));
+        IGR_TRY((flux_impl<F, MODE_STAGE3, true>(c, U, Ub, cur, nullptr, Unew, dtp, dt_fixed, s, speed,
+                                                 cur != sig ? sig : nullptr)));
+    } else {
+        // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
+        IGR_TRY(fill_state_ghosts(c, Ua, s));
+        IGR_TRY(solve(NoD{}, Ua, nullptr));
+        IGR_TRY((flux_impl<F, MODE_STAGE2>(c, Ua, nullptr, cur, U, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, nullptr, Ub, dtp, dt_fixed, s)));
+        // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
+        // solve ended in the scratch copy the kernel also writes Sigma's interior
+        // into the caller's buffer (its ghosts are scratch)
+        IGR_TRY(fill_state_ghosts(c, Ub, s));
+        IGR_TRY(solve(NoD{}, Ub, nullptr));
+        IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s, speed,
+                                           cur != sig ? sig : nullptr)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s)));
+    }
     return IGR_OK;
 }
 
-template <class T>
-int step_impl(igr_ctx* c, T* U, T* sig, double cfl, double dt_fixed, hipStream_t s) {
-    if (!(dt_fixed > 0.0)) return step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr, true, cfl);
-    return step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr);
+// The state a step writes: in place, or the split form's other FP32 state.
+template <class F>
+typename F::TB* next_state(igr_ctx* c, typename F::TB* U, typename F::TB* Ucaller) {
+    if constexpr (F::SPLIT)
+        return U == Ucaller ? static_cast<typename F::TB*>(c->d_Unb) : Ucaller;
+    else
+        return U;
+}
+
+// Copies a split-form result from the other FP32 state into the caller's U.
+template <class F>
+int settle_state(igr_ctx* c, typename F::TB* U, typename F::TB* Ucaller, hipStream_t s) {
+    if (U != Ucaller)
+        IGR_HIP(hipMemcpyAsync(Ucaller, U, 5 * field_bytes(c, sizeof(typename F::TB)), hipMemcpyDeviceToDevice, s));
+    return IGR_OK;
+}
+
+template <class F>
+int step_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, double cfl, double dt_fixed, hipStream_t s) {
+    typename F::TB* Unew = next_state<F>(c, U, U);
+    if (!(dt_fixed > 0.0))
+        IGR_TRY(step_stages<F>(c, U, Unew, sig, nullptr, dt_fixed, s, nullptr, true, cfl));
+    else
+        IGR_TRY(step_stages<F>(c, U, Unew, sig, nullptr, dt_fixed, s, nullptr));
+    return settle_state<F>(c, Unew, U, s);
 }
 
 // nsteps steps.  With a CFL time step in the forms with FP32 arithmetic,
 // the first step's maximum comes from the standalone reduction and every
 // later one from the maxima that the previous step's last stage left in
-// d_speed.  FP64 forms each step's maxima in its first sweep instead (the
-// FP64 flux kernel is at its register limit: fused there it spills).
-template <class T>
-int advance_impl(igr_ctx* c, T* U, T* sig, int nsteps, double cfl, double dt_fixed, hipStream_t s) {
+// d_speed (with viscous terms, which the last stage adds after the flux
+// kernel, every step runs the standalone reduction).  FP64 forms each step's maxima in its first sweep instead (the
+// FP64 flux kernel is at its register limit: fused there it spills).  The
+// split form alternates between the caller's U and its other FP32 state and
+// copies the last state into U if it ends in the other one.
+template <class F>
+int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int nsteps, double cfl, double dt_fixed,
+                 hipStream_t s) {
+    using TB = typename F::TB;
     const bool use_cfl = !(dt_fixed > 0.0);
-    constexpr bool fused = sizeof(typename Storage<T>::C) == 4;
-    const int nblk = int(flux_blocks<T>(c));
+    const bool fused = sizeof(typename F::C) == 4 && !c->viscous;
+    const int nblk = int(flux_blocks<F>(c));
+    TB* U = Ucaller;
     for (int n = 0; n < nsteps; ++n) {
+        TB* Unew = next_state<F>(c, U, Ucaller);
         const double* dtp = nullptr;
         if (use_cfl && !fused) {
-            IGR_TRY(step_stages(c, U, sig, nullptr, dt_fixed, s, nullptr, true, cfl));
+            IGR_TRY(step_stages<F>(c, U, Unew, sig, nullptr, dt_fixed, s, nullptr, true, cfl));
+            U = Unew;
             continue;
         }
         if (use_cfl) {
             if (n == 0) {
-                IGR_TRY(speed_dt_impl(c, U, cfl, s));
+                IGR_TRY(speed_dt_impl(c, (const TB*)U, cfl, s));
             } else {
                 IGR_TRY(launch(c, K_DT, s, [&] {
                     k_dt_final<<<1, RED_THREADS, 0, s>>>(c->d_speed, nblk, cfl, c->d_scalars);
@@ -604,9 +733,11 @@ int advance_impl(igr_ctx* c, T* U, T* sig, int nsteps, double cfl, double dt_fix
             }
             dtp = c->d_scalars;
         }
-        IGR_TRY(step_stages(c, U, sig, dtp, dt_fixed, s, fused && use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
+        IGR_TRY(step_stages<F>(c, U, Unew, sig, dtp, dt_fixed, s,
+                               fused && use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
+        U = Unew;
     }
-    return IGR_OK;
+    return settle_state<F>(c, U, Ucaller, s);
 }
 
 template <class T>
@@ -620,12 +751,13 @@ int sums_impl(igr_ctx* c, const T* U, double out[5], hipStream_t s) {
     return IGR_OK;
 }
 
-template <class T>
-int resid_impl(igr_ctx* c, const T* U, const T* sig, double* out, hipStream_t s) {
-    using C = typename Storage<T>::C;
+template <class F>
+int resid_impl(igr_ctx* c, const typename F::TB* U, const typename F::TS* sig, double* out, hipStream_t s) {
+    using C = typename F::C;
     const C* b = static_cast<const C*>(c->d_b);
     IGR_TRY(launch(c, K_RESID, s, [&] {
-        k_resid_partial<T, C><<<RED_BLOCKS, RED_THREADS, 0, s>>>(sig, b, U, c->g, c->d_partial);
+        k_resid_partial<typename F::TS, typename F::TB, C>
+            <<<RED_BLOCKS, RED_THREADS, 0, s>>>(sig, b, U, c->g, c->d_partial);
         k_sum_final<1><<<1, RED_THREADS, 0, s>>>(c->d_partial, RED_BLOCKS, 1.0, c->d_scalars + 6);
     }));
     double r2 = 0.0;
@@ -686,8 +818,9 @@ int upload_jets(igr_ctx* c, hipStream_t s, bool sync) {
 
 void release(igr_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_owner, c->d_chi,     c->d_jet,     c->d_Ua,   c->d_Ub,   c->d_sig2,
-                    c->d_b,     c->d_ir,      c->d_partial, c->d_scalars, c->d_flag, c->d_speed};
+    void* ptrs[] = {c->d_owner, c->d_chi,     c->d_jet,      c->d_Ua,   c->d_Ub,    c->d_sig2, c->d_b,
+                    c->d_ir,    c->d_partial, c->d_scalars,  c->d_flag, c->d_speed, c->d_Unb,  c->d_jet0,
+                    c->d_G};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (double* p : c->adj)
@@ -704,40 +837,45 @@ void release(igr_ctx* c) {
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 #define DISPATCH(ctx, FN, ...)                                                                        \
-    ((ctx)->precision == IGR_F64    ? FN<double>(__VA_ARGS__)                                         \
-     : (ctx)->precision == IGR_F32  ? FN<float>(__VA_ARGS__)                                          \
-     : (ctx)->precision == IGR_F16_F32 ? FN<f16>(__VA_ARGS__)                                         \
-                                    : FN<bf16>(__VA_ARGS__))
+    ((ctx)->precision == IGR_F64          ? FN<Plain<double>>(__VA_ARGS__)                            \
+     : (ctx)->precision == IGR_F32        ? FN<Plain<float>>(__VA_ARGS__)                             \
+     : (ctx)->precision == IGR_F16_F32    ? FN<Plain<f16>>(__VA_ARGS__)                               \
+     : (ctx)->precision == IGR_F32_BF16D  ? FN<Split>(__VA_ARGS__)                                    \
+                                          : FN<Plain<bf16>>(__VA_ARGS__))
 
-template <class T>
+template <class F>
 int rhs_t(igr_ctx* c, void* U, void* sig, void* rhs, hipStream_t s) {
-    return rhs_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), static_cast<T*>(rhs), s);
+    return rhs_impl<F>(c, static_cast<typename F::TB*>(U), static_cast<typename F::TS*>(sig),
+                       static_cast<typename F::TB*>(rhs), s);
 }
-template <class T>
+template <class F>
 int step_t(igr_ctx* c, void* U, void* sig, double cfl, double dt_fixed, hipStream_t s) {
-    return step_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), cfl, dt_fixed, s);
+    return step_impl<F>(c, static_cast<typename F::TB*>(U), static_cast<typename F::TS*>(sig), cfl, dt_fixed, s);
 }
-template <class T>
+template <class F>
 int advance_t(igr_ctx* c, void* U, void* sig, int nsteps, double cfl, double dt_fixed, hipStream_t s) {
-    return advance_impl<T>(c, static_cast<T*>(U), static_cast<T*>(sig), nsteps, cfl, dt_fixed, s);
+    return advance_impl<F>(c, static_cast<typename F::TB*>(U), static_cast<typename F::TS*>(sig), nsteps, cfl,
+                           dt_fixed, s);
 }
-template <class T>
+template <class F>
 int sigma_t(igr_ctx* c, void* U, void* sig, int nsweeps, double* resid, hipStream_t s) {
-    IGR_TRY(fill_state_ghosts(c, static_cast<T*>(U), s));
-    IGR_TRY(sigma_solve_impl(c, static_cast<T*>(U), static_cast<T*>(sig), nsweeps, s));
+    using TB = typename F::TB;
+    using TS = typename F::TS;
+    IGR_TRY(fill_state_ghosts(c, static_cast<TB*>(U), s));
+    IGR_TRY(sigma_solve_impl<F>(c, static_cast<TB*>(U), static_cast<TS*>(sig), nsweeps, s));
     if (resid) {
-        IGR_TRY(source_impl(c, static_cast<const T*>(U), s));
-        IGR_TRY(resid_impl(c, static_cast<const T*>(U), static_cast<const T*>(sig), resid, s));
+        IGR_TRY(source_impl(c, static_cast<const TB*>(U), s));
+        IGR_TRY(resid_impl<F>(c, static_cast<const TB*>(U), static_cast<const TS*>(sig), resid, s));
     }
     return IGR_OK;
 }
-template <class T>
+template <class F>
 int dt_t(igr_ctx* c, const void* U, double cfl, hipStream_t s) {
-    return speed_dt_impl(c, static_cast<const T*>(U), cfl, s);
+    return speed_dt_impl(c, static_cast<const typename F::TB*>(U), cfl, s);
 }
-template <class T>
+template <class F>
 int sums_t(igr_ctx* c, const void* U, double* out, hipStream_t s) {
-    return sums_impl(c, static_cast<const T*>(U), out, s);
+    return sums_impl(c, static_cast<const typename F::TB*>(U), out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -984,8 +1122,13 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
             return fail(IGR_EINVAL, "inflow disc needs r >= 0, width >= 0, rho > 0, p > 0");
     }
     if (opts->precision != IGR_F64 && opts->precision != IGR_F32 && opts->precision != IGR_BF16_F32 &&
-        opts->precision != IGR_F16_F32)
+        opts->precision != IGR_F16_F32 && opts->precision != IGR_F32_BF16D)
         return fail(IGR_EINVAL, "unknown precision");
+    if (opts->precision == IGR_F32_BF16D && opts->sigma_block > 2)
+        return fail(IGR_EUNSUPPORTED, "IGR_F32_BF16D runs single or two-sweep Sigma passes (sigma_block 0..2)");
+    if (!(opts->mu >= 0.0) || !(opts->zeta >= 0.0)) return fail(IGR_EINVAL, "viscosities must be >= 0");
+    if ((opts->mu > 0.0 || opts->zeta > 0.0) && opts->precision != IGR_F64 && opts->precision != IGR_F32)
+        return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
     if (opts->order != 5 && opts->order != 3)
         return fail(IGR_EUNSUPPORTED, "reconstruction order must be 5 or 3");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
@@ -1011,6 +1154,9 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     c->nsweeps = opts->nsweeps;
     c->order = opts->order;
     c->smoother = opts->smoother;
+    c->mu = opts->mu;
+    c->zeta = opts->zeta;
+    c->viscous = opts->mu > 0.0 || opts->zeta > 0.0;
     c->sigma_block = opts->sigma_block;   // 0: resolved below, once the field size is known
     for (int f = 0; f < 6; ++f) c->faces[f] = bc->face[f];
     c->patches.assign(bc->patch, bc->patch + bc->npatch);
@@ -1033,16 +1179,20 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     g.gamma = gamma;
     g.alpha = alpha;
     for (int d = 0; d < 3; ++d) g.periodic[d] = bc->face[2 * d] == IGR_BC_PERIODIC;
-    c->esize = c->precision == IGR_F64 ? 8 : c->precision == IGR_F32 ? 4 : 2;   // BF16 and F16: 2
+    const bool split = c->precision == IGR_F32_BF16D;
+    c->esize = c->precision == IGR_F64 ? 8 : (c->precision == IGR_F32 || split) ? 4 : 2;   // BF16 and F16: 2
+    c->dsize = split ? 2 : c->esize;
+    c->ssize = split ? 2 : c->esize;
     c->csize = c->precision == IGR_F64 ? 8 : 4;
     if (c->sigma_block == 0) {
         // Two sweeps per pass halve the sweeps' memory traffic but cost
         // more instructions per sweep.  In FP64 the sweeps are bound by
         // memory at every size.  With FP32 arithmetic the single-sweep
-        // kernel wins while one sweep's working set (Sigma in and out, rho,
-        // the FP32 source) stays in the last-level cache, whose reuse the
-        // two-sweep pass cannot improve on.
-        const double sweep_bytes = double(g.fs) * (3.0 * c->esize + c->csize);
+        // kernel wins while one sweep's working set (Sigma in and out, rho
+        // or the stored 1/rho, the FP32 source) stays in the last-level
+        // cache, whose reuse the two-sweep pass cannot improve on.
+        const double rho_bytes = split ? double(c->csize) : double(c->esize);
+        const double sweep_bytes = double(g.fs) * (2.0 * c->ssize + rho_bytes + c->csize);
         c->sigma_block = (c->precision == IGR_F64 || sweep_bytes > IGR_LLC_BYTES) ? 2 : 1;
     }
 
@@ -1054,18 +1204,22 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     };
     int rc = IGR_OK;
     if (hipGetDevice(&c->device) != hipSuccess) rc = fail(IGR_EHIP, "hipGetDevice failed");
-    if (!rc) rc = alloc(&c->d_Ua, 5 * field_bytes(c, c->esize));
-    if (!rc) rc = alloc(&c->d_Ub, 5 * field_bytes(c, c->esize));
-    if (!rc) rc = alloc(&c->d_sig2, field_bytes(c, c->esize));
+    if (!rc) rc = alloc(&c->d_Ua, 5 * field_bytes(c, c->dsize));
+    if (!rc) rc = alloc(&c->d_Ub, 5 * field_bytes(c, c->dsize));
+    if (!rc) rc = alloc(&c->d_sig2, field_bytes(c, c->ssize));
     if (!rc) rc = alloc(&c->d_b, field_bytes(c, c->csize));
-    if (!rc && c->precision == IGR_F64) rc = alloc(&c->d_ir, field_bytes(c, sizeof(double)));
+    if (!rc && (c->precision == IGR_F64 || split)) rc = alloc(&c->d_ir, field_bytes(c, c->csize));
+    if (!rc && split) rc = alloc(&c->d_Unb, 5 * field_bytes(c, c->esize));
+    if (!rc && c->viscous) rc = alloc(&c->d_G, 9 * field_bytes(c, c->csize));
     if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
     if (!rc) {
         // per-block CFL maxima: of the last flux stage (FP32 arithmetic) or
         // of the first sweep (FP64)
-        long long nb = c->precision == IGR_F64 ? flux_blocks<double>(c) : flux_blocks<float>(c);
+        long long nb = c->precision == IGR_F64         ? flux_blocks<Plain<double>>(c)
+                       : c->precision == IGR_F32_BF16D ? flux_blocks<Split>(c)
+                                                       : flux_blocks<Plain<float>>(c);
         if (c->precision == IGR_F64 && sweep_speed_slots(c->g) > nb) nb = sweep_speed_slots(c->g);
         rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
     }
@@ -1074,14 +1228,19 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
         rc = alloc((void**)&c->d_owner, cols * sizeof(int));
         if (!rc) rc = alloc((void**)&c->d_chi, cols * sizeof(double));
         if (!rc) rc = alloc((void**)&c->d_jet, c->patches.size() * 5 * sizeof(double));
+        if (!rc) rc = alloc((void**)&c->d_jet0, c->patches.size() * 5 * sizeof(double));
+        if (!rc && hipMemset(c->d_jet0, 0, c->patches.size() * 5 * sizeof(double)) != hipSuccess)
+            rc = fail(IGR_EHIP, "zero jet table initialisation failed");
         if (!rc) rc = upload_patches(c);
         if (!rc) rc = upload_jets(c, nullptr, true);
     }
     if (!rc) {
         // scratch starts defined: zero states, Sigma copy and source
-        if (hipMemset(c->d_Ua, 0, 5 * field_bytes(c, c->esize)) != hipSuccess ||
-            hipMemset(c->d_Ub, 0, 5 * field_bytes(c, c->esize)) != hipSuccess ||
-            hipMemset(c->d_sig2, 0, field_bytes(c, c->esize)) != hipSuccess ||
+        if (hipMemset(c->d_Ua, 0, 5 * field_bytes(c, c->dsize)) != hipSuccess ||
+            hipMemset(c->d_Ub, 0, 5 * field_bytes(c, c->dsize)) != hipSuccess ||
+            hipMemset(c->d_sig2, 0, field_bytes(c, c->ssize)) != hipSuccess ||
+            (split && hipMemset(c->d_Unb, 0, 5 * field_bytes(c, c->esize)) != hipSuccess) ||
+            (c->viscous && hipMemset(c->d_G, 0, 9 * field_bytes(c, c->csize)) != hipSuccess) ||
             hipMemset(c->d_b, 0, field_bytes(c, c->csize)) != hipSuccess ||
             hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             rc = fail(IGR_EHIP, "scratch initialisation failed");
@@ -1116,6 +1275,8 @@ int igr_get_opts(const igr_ctx* ctx, igr_opts* out) {
     out->nsweeps = ctx->nsweeps;
     out->sigma_block = ctx->sigma_block;
     out->smoother = ctx->smoother;
+    out->mu = ctx->mu;
+    out->zeta = ctx->zeta;
     return IGR_OK;
 }
 
@@ -1231,6 +1392,7 @@ int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* r
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
+    if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
     // inputs may alias outputs: stage them
@@ -1257,6 +1419,7 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
+    if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
@@ -1273,12 +1436,12 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     // forward recompute of the stage states and stage warm starts
     IGR_TRY(fill_state_ghosts(ctx, Un, s));
     IGR_TRY(dcopy(ctx, sig1, (const double*)sigma_n, 1, s));
-    IGR_TRY(sigma_solve_impl(ctx, Un, sig1, S, s));
-    IGR_TRY((flux_impl<double, MODE_STAGE1>(ctx, Un, sig1, nullptr, U1, nullptr, dt, s)));
+    IGR_TRY(sigma_solve_impl<Plain<double>>(ctx, Un, sig1, S, s));
+    IGR_TRY((flux_impl<Plain<double>, MODE_STAGE1>(ctx, Un, nullptr, sig1, nullptr, U1, nullptr, dt, s)));
     IGR_TRY(fill_state_ghosts(ctx, U1, s));
     IGR_TRY(dcopy(ctx, sig2, sig1, 1, s));
-    IGR_TRY(sigma_solve_impl(ctx, U1, sig2, S, s));
-    IGR_TRY((flux_impl<double, MODE_STAGE2>(ctx, U1, sig2, Un, U2, nullptr, dt, s)));
+    IGR_TRY(sigma_solve_impl<Plain<double>>(ctx, U1, sig2, S, s));
+    IGR_TRY((flux_impl<Plain<double>, MODE_STAGE2>(ctx, U1, nullptr, sig2, Un, U2, nullptr, dt, s)));
     // reverse sweep over the stages
     double* Ubn = abuf(ctx, A_UBN);
     double* Ub1 = abuf(ctx, A_UB1);
@@ -1321,7 +1484,8 @@ int igr_compute_dt_noalloc(const igr_grid* grid, double gamma, int32_t precision
     if (!(grid->dx > 0) || !(grid->dy > 0) || !(grid->dz > 0)) return fail(IGR_EINVAL, "spacings must be > 0");
     if (!(gamma > 1.0)) return fail(IGR_EINVAL, "gamma must be > 1");
     if (!(cfl > 0.0)) return fail(IGR_EINVAL, "cfl must be > 0");
-    if (precision != IGR_F64 && precision != IGR_F32 && precision != IGR_BF16_F32 && precision != IGR_F16_F32)
+    if (precision != IGR_F64 && precision != IGR_F32 && precision != IGR_BF16_F32 && precision != IGR_F16_F32 &&
+        precision != IGR_F32_BF16D)
         return fail(IGR_EINVAL, "unknown precision");
     const long long px = grid->nx + 2 * G, py = grid->ny + 2 * G, pz = grid->nz + 2 * G;
     if (px * py > 0x7fffffffLL) return fail(IGR_EINVAL, "x-y plane too large");
@@ -1347,7 +1511,7 @@ int igr_compute_dt_noalloc(const igr_grid* grid, double gamma, int32_t precision
     int* flag = reinterpret_cast<int*>(base + kNoAllocFlagOff);
     hipStream_t s = as_stream(stream);
     IGR_TRY(precision == IGR_F64   ? dt_noalloc_t<double>(g, U, partial, result, flag, cfl, s)
-            : precision == IGR_F32 ? dt_noalloc_t<float>(g, U, partial, result, flag, cfl, s)
+            : (precision == IGR_F32 || precision == IGR_F32_BF16D) ? dt_noalloc_t<float>(g, U, partial, result, flag, cfl, s)
             : precision == IGR_F16_F32 ? dt_noalloc_t<f16>(g, U, partial, result, flag, cfl, s)
                                        : dt_noalloc_t<bf16>(g, U, partial, result, flag, cfl, s));
     int bad = 0;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace igr {
 
 constexpr int G = 3;  // ghost layers (five-point upwind reconstruction)
@@ -72,6 +74,86 @@ struct Storage<f16> {
     __device__ __forceinline__ static float load(const f16* p) { return float(*p); }
     __device__ __forceinline__ static void store(f16* p, float v) { *p = f16(v); }
     __device__ __forceinline__ static C stored(C v) { return float(f16(v)); }
+};
+
+// Storage forms: how the kernels read a stage state and Sigma.  A kernel
+// reads a state value through load_u (base array plus, with HASD, a
+// difference array) and a Sigma value through load_s, keeps the register
+// form RU until the value is used and widens it with cvt.
+//
+// Plain<T>: the state, every RK stage state and Sigma are stored in T (the
+// difference array is never read).
+template <class T>
+struct Plain {
+    using S = Storage<T>;
+    using C = typename S::C;
+    using TB = T;   // the step's state U^n (the caller's U) and rhs
+    using TD = T;   // RK stage state buffers
+    using TS = T;   // Sigma
+    using RU = typename S::R;
+    static constexpr bool SPLIT = false;
+    // the first sweep of a solve stores 1/rho for the later sweeps (FP64)
+    static constexpr bool IRS = sizeof(C) == 8;
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_u(const TB* b, const TD*, long long o) {
+        return S::load_raw(b + o);
+    }
+    __device__ __forceinline__ static RU load_s(const TS* s, long long o) { return S::load_raw(s + o); }
+    // field f of (U, Sigma): 0..4 the state, 5 Sigma
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_field(const TB* b, const TD*, const TS* s, int f, long long fs,
+                                                    long long o) {
+        return S::load_raw((f < 5 ? b + f * fs : s) + o);
+    }
+    __device__ __forceinline__ static C cvt(RU r) { return S::cvt(r); }
+};
+
+// Split: FP32 arithmetic; the step's state U^n is FP32, each later RK stage
+// state is stored as its bfloat16 difference from U^n (the stage value is
+// U^n + delta, summed in FP32), Sigma is bfloat16.  Rounding a whole stage
+// state to 8 significand bits loses 2^-9 of the state at every stage, and
+// that accumulates over the steps; rounding its difference from U^n loses
+// 2^-9 of the difference only, and U^n itself is rounded to FP32 once per
+// step.  Stage 1 reads U^n alone (HASD false).
+struct Split {
+    using C = float;
+    using TB = float;
+    using TD = bf16;
+    using TS = bf16;
+    struct RU {
+        float a;      // base value (0 for Sigma)
+        uint32_t d;   // bfloat16 bits of the difference (of Sigma itself)
+    };
+    static constexpr bool SPLIT = true;
+    static constexpr bool IRS = true;
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_u(const float* b, const bf16* d, long long o) {
+        RU r;
+        r.a = b[o];
+        if constexpr (HASD)
+            r.d = d[o].bits;
+        else
+            r.d = 0u;
+        return r;
+    }
+    __device__ __forceinline__ static RU load_s(const bf16* s, long long o) {
+        RU r;
+        r.a = 0.0f;
+        r.d = s[o].bits;
+        return r;
+    }
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_field(const float* b, const bf16* d, const bf16* s, int f, long long fs,
+                                                    long long o) {
+        RU r;
+        r.a = f < 5 ? b[f * fs + o] : 0.0f;
+        if constexpr (HASD)
+            r.d = (f < 5 ? d + f * fs : s)[o].bits;
+        else
+            r.d = f < 5 ? 0u : uint32_t(s[o].bits);
+        return r;
+    }
+    __device__ __forceinline__ static C cvt(RU r) { return r.a + __uint_as_float(r.d << 16); }
 };
 
 // Reciprocal for finite positive arguments.  FP64: the hardware estimate

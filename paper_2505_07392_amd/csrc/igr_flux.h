@@ -48,13 +48,28 @@ __device__ __forceinline__ void face_flux6(const C (&v)[6][6], int d, C gamma, C
     llf_flux<C>(UL, UR, Q[5][0], Q[5][1], d, gamma, F, bad);
 }
 
-template <class T, int MODE, int TY, int ORDER>
+// Element type of a stage's output: the state's type, except the stage
+// buffers of the split form (the bfloat16 differences from U^n).
+template <class F, int MODE>
+using FluxOut = std::conditional_t<F::SPLIT && (MODE == MODE_STAGE1 || MODE == MODE_STAGE2), typename F::TD,
+                                   typename F::TB>;
+
+// F: storage form (Plain<T> or Split).  The stage input is U (+ D with
+// HASD, the split form's stage difference); Un is U^n for the pointwise
+// reads of stages 2 and 3 of the plain forms (the split form reads U and D
+// there).  Split outputs: stage 1 and 2 write the difference of the next
+// stage state from U^n, stage 3 writes U^(n+1) (FP32, not in place: the
+// stencil still reads U^n).
+template <class F, int MODE, int TY, int ORDER, bool HASD = false>
 __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
-    const T* __restrict__ U, const T* __restrict__ Sg, const T* Un, T* out, const double* __restrict__ dtp,
-    double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y, int zc,
-    double* __restrict__ speed, T* __restrict__ sig_out) {
-    using S = Storage<T>;
-    using C = typename S::C;
+    const typename F::TB* __restrict__ U, const typename F::TD* __restrict__ D,
+    const typename F::TS* __restrict__ Sg, const typename F::TB* Un, FluxOut<F, MODE>* out,
+    const double* __restrict__ dtp, double dt_fixed, Geom g, int* __restrict__ flag, int tiles_x, int tiles_y,
+    int zc, double* __restrict__ speed, typename F::TS* __restrict__ sig_out) {
+    using C = typename F::C;
+    using RU = typename F::RU;
+    using SO = Storage<FluxOut<F, MODE>>;
+    using SS = Storage<typename F::TS>;
     constexpr int TX = FLUX_TX;
     constexpr int W = TX + 2 * G;
     constexpr int H = TY + 2 * G;
@@ -108,30 +123,29 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
     for (int f = 0; f < 5; ++f) Fz_prev[f] = C(0);
 
-    // prefetched values stay in the storage's register form R until used
+    // prefetched values stay in the storage's register form RU until used
     // (a 16-bit value converted at its load would wait for that load)
-    using R = typename S::R;
-    auto load_col = [&](int plane, R (&v)[6]) {
+    auto load_col = [&](int plane, RU (&v)[6]) {
         const long long o = col + (long long)(plane + G) * sz;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) v[f] = S::load_raw(U + f * fs + o);
-        v[5] = S::load_raw(Sg + o);
+        for (int f = 0; f < 5; ++f) v[f] = F::template load_u<HASD>(U, D, f * fs + o);
+        v[5] = F::load_s(Sg, o);
     };
     // prime with planes z0-3 .. z0+1 (slot p holds plane z0-3+p) and keep
     // plane z0+2 in `nxt`; every iteration shifts, moves `nxt` into slot 5
     // and issues the load of the plane after it, so each column load has a
     // whole iteration to arrive.  The loop starts at k = z0 - 1 to compute
     // face z0 - 1/2 with the same code as every other z face.
-    R nxt[6];
+    RU nxt[6];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) nxt[f] = R(0);
+    for (int f = 0; f < 6; ++f) nxt[f] = RU{};
     if (col_load) {
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
-            R v[6];
+            RU v[6];
             load_col(z0 - 3 + p, v);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) q[f][p + 1] = S::cvt(v[f]);
+            for (int f = 0; f < 6; ++f) q[f][p + 1] = F::cvt(v[f]);
         }
         load_col(z0 + 2, nxt);
     }
@@ -144,7 +158,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     constexpr int NYR = 6 * 2 * G;               // y-halo rows over all fields
     constexpr int HY = (NYR + NW - 1) / NW;      // y-halo rows per wave
     constexpr int NXH = 6 * 2 * G * TY;          // x-halo cells over all fields
-    R hy[HY], hx = R(0);
+    RU hy[HY], hx = RU{};
     auto y_slot = [&](int s, int& f, int& cy) -> bool {
         const int rf = wv + s * NW;
         if (rf >= NYR) return false;
@@ -164,27 +178,31 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         const int gx = x0 + cx;
         return gx >= -G && gx < nx + G && (y0 + cy) < ny + G;
     };
-    auto fld = [&](int f) { return f < 5 ? U + f * fs : Sg; };
     auto load_halo = [&](int plane) {
         const long long zo = (long long)(plane + G) * sz;
 #pragma unroll
         for (int s = 0; s < HY; ++s) {
             int f, cy;
-            hy[s] = R(0);
-            if (y_slot(s, f, cy)) hy[s] = S::load_raw(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
+            hy[s] = RU{};
+            if (y_slot(s, f, cy))
+                hy[s] = F::template load_field<HASD>(U, D, Sg, f, fs, zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
         }
         int f, cx, cy;
-        hx = R(0);
-        if (x_slot(f, cx, cy)) hx = S::load_raw(fld(f) + zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G));
+        hx = RU{};
+        if (x_slot(f, cx, cy))
+            hx = F::template load_field<HASD>(U, D, Sg, f, fs, zo + (long long)(y0 + cy + G) * sy + (x0 + cx + G));
     };
     load_halo(z0);
 
-    C unv[5];
-    R un_next[5];
+    // pointwise values of stages 2 and 3: plain forms U^n (unv); split form
+    // the stage's difference from U^n (und)
+    C unv[5], und[5];
+    RU un_next[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
         unv[f] = C(0);
-        un_next[f] = R(0);
+        und[f] = C(0);
+        un_next[f] = RU{};
     }
     for (int k = z0 - 1; k < z1; ++k) {
         // shift the queue; slots hold k-2..k+3 afterwards
@@ -192,17 +210,27 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         for (int f = 0; f < 6; ++f) {
 #pragma unroll
             for (int p = 0; p < 5; ++p) q[f][p] = q[f][p + 1];
-            if (col_load) q[f][5] = S::cvt(nxt[f]);
+            if (col_load) q[f][5] = F::cvt(nxt[f]);
         }
         if (col_load && k + 1 < z1) load_col(k + 4, nxt);
         // Un (read pointwise by stages 2 and 3) is fetched one plane ahead
         if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) unv[f] = S::cvt(un_next[f]);
+            for (int f = 0; f < 5; ++f) {
+                if constexpr (F::SPLIT)
+                    und[f] = F::cvt(RU{0.0f, un_next[f].d});
+                else
+                    unv[f] = F::cvt(un_next[f]);
+            }
             if (col_out && k + 1 < z1) {
                 const long long o = col + (long long)(k + 1 + G) * sz;
 #pragma unroll
-                for (int f = 0; f < 5; ++f) un_next[f] = S::load_raw(Un + f * fs + o);
+                for (int f = 0; f < 5; ++f) {
+                    if constexpr (F::SPLIT)
+                        un_next[f].d = D[f * fs + o].bits;
+                    else
+                        un_next[f] = F::template load_u<false>(Un, nullptr, f * fs + o);
+                }
             }
         }
         const bool body = k >= z0;
@@ -216,11 +244,11 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
             for (int s = 0; s < HY; ++s) {
                 int f, cy;
-                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = S::cvt(hy[s]);
+                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = F::cvt(hy[s]);
             }
             {
                 int f, cx, cy;
-                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = S::cvt(hx);
+                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = F::cvt(hx);
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
@@ -241,10 +269,10 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                         for (int f = 0; f < 6; ++f)
 #pragma unroll
                             for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi + p];
-                        C F[5];
-                        face_flux6<C, ORDER>(v, 0, gamma, F, bad);
+                        C Fl[5];
+                        face_flux6<C, ORDER>(v, 0, gamma, Fl, bad);
 #pragma unroll
-                        for (int f = 0; f < 5; ++f) fx[f][r][fi] = F[f];
+                        for (int f = 0; f < 5; ++f) fx[f][r][fi] = Fl[f];
                     }
                 }
                 // B2: y faces (y0+wv)-1/2 for wv = 0..TY, column lane
@@ -257,10 +285,10 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                         for (int f = 0; f < 6; ++f)
 #pragma unroll
                             for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
-                        C F[5];
-                        face_flux6<C, ORDER>(v, 1, gamma, F, bad);
+                        C Fl[5];
+                        face_flux6<C, ORDER>(v, 1, gamma, Fl, bad);
 #pragma unroll
-                        for (int f = 0; f < 5; ++f) fy[f][wv][lane] = F[f];
+                        for (int f = 0; f < 5; ++f) fy[f][wv][lane] = Fl[f];
                     }
                 }
             }
@@ -296,6 +324,18 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     C v;
                     if (MODE == MODE_RHS) {
                         v = L[f];
+                    } else if constexpr (F::SPLIT) {
+                        // differences from U^n: U1 - Un = dt L(Un);
+                        // U2 - Un = 1/4 ((U1 - Un) + dt L(U1)); and
+                        // Un+1 = Un + 2/3 ((U2 - Un) + dt L(U2))
+                        //      = U2 + 2/3 dt L(U2) - 1/3 (U2 - Un)
+                        // with U2 the stencil's centre value (Un + delta in FP32)
+                        if (MODE == MODE_STAGE1)
+                            v = dt * L[f];
+                        else if (MODE == MODE_STAGE2)
+                            v = C(0.25) * (und[f] + dt * L[f]);
+                        else
+                            v = q[f][2] + ((C(2) / C(3)) * (dt * L[f]) - (C(1) / C(3)) * und[f]);
                     } else if (MODE == MODE_STAGE1) {
                         v = q[f][2] + dt * L[f];
                     } else if (MODE == MODE_STAGE2) {
@@ -303,12 +343,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     } else {
                         v = unv[f] * (C(1) / C(3)) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
                     }
-                    S::store(out + of, v);
-                    if (FUSE) vs[f] = double(S::stored(v));
+                    SO::store(out + of, v);
+                    if (FUSE) vs[f] = double(SO::stored(v));
                 }
                 // last stage: the solved Sigma of this plane into the caller's
                 // buffer when the solve ended in the scratch copy
-                if (MODE == MODE_STAGE3 && sig_out != nullptr) S::store(sig_out + o, q[5][2]);
+                if (MODE == MODE_STAGE3 && sig_out != nullptr) SS::store(sig_out + o, q[5][2]);
                 // last stage: CFL speed of the new state as stored (for the
                 // next step's dt), when the caller asked for it
                 if (FUSE && speed != nullptr)

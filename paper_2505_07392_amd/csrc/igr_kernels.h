@@ -367,26 +367,28 @@ __global__ void k_sum_final(const double* __restrict__ partial, int nblocks, dou
         for (int c = 0; c < NV; ++c) out[c] = v[c] * scale;
 }
 
-// Squared residual of eq. (9)'s discretisation, r = b - A Sigma, in FP64.
-template <class T, class C>
-__global__ void k_resid_partial(const T* __restrict__ Sg, const C* __restrict__ b, const T* __restrict__ rho,
+// Squared residual of eq. (9)'s discretisation, r = b - A Sigma, in FP64
+// (Sigma stored as TS, rho as TR).
+template <class TS, class TR, class C>
+__global__ void k_resid_partial(const TS* __restrict__ Sg, const C* __restrict__ b, const TR* __restrict__ rho,
                                 Geom g, double* __restrict__ partial) {
-    using S = Storage<T>;
+    using SS = Storage<TS>;
+    using SR = Storage<TR>;
     const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
     double v[1] = {0.0};
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
          t += (long long)gridDim.x * blockDim.x) {
         const int idx[3] = {int(t % g.n[0]), int((t / g.n[0]) % g.n[1]), int(t / g.n[0] / g.n[1])};
         const long long o = cell_offset(g, idx[0], idx[1], idx[2]);
-        const double ic = 1.0 / double(S::load(rho + o));
-        const double sc = double(S::load(Sg + o));
+        const double ic = 1.0 / double(SR::load(rho + o));
+        const double sc = double(SS::load(Sg + o));
         double a = sc * ic;
         for (int d = 0; d < 3; ++d) {
             const double h2 = g.ih[d] * g.ih[d];
-            const double bp = 0.5 * (ic + 1.0 / double(S::load(rho + o + g.st[d])));
-            const double bm = 0.5 * (ic + 1.0 / double(S::load(rho + o - g.st[d])));
-            const double sp = double(S::load(Sg + o + neighbour_no_ghost(g, d, idx[d], +1)));
-            const double sm = double(S::load(Sg + o + neighbour_no_ghost(g, d, idx[d], -1)));
+            const double bp = 0.5 * (ic + 1.0 / double(SR::load(rho + o + g.st[d])));
+            const double bm = 0.5 * (ic + 1.0 / double(SR::load(rho + o - g.st[d])));
+            const double sp = double(SS::load(Sg + o + neighbour_no_ghost(g, d, idx[d], +1)));
+            const double sm = double(SS::load(Sg + o + neighbour_no_ghost(g, d, idx[d], -1)));
             a -= g.alpha * (bp * (sp - sc) - bm * (sc - sm)) * h2;
         }
         const double r = double(b[o]) - a;

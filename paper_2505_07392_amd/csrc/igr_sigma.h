@@ -287,20 +287,26 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
 // Values are kept in the storage's register form R (converted where used)
 // so that a conversion does not wait for its load.  In FP64 later sweeps
 // `rho` holds the stored 1/rho.
-template <class T, bool FIRST>
+// In the later sweeps of a form that stores 1/rho (IRS), `rho` holds the
+// stored 1/rho (arithmetic type) instead of a loaded state value.
+template <class F, bool FIRST>
 struct SweepCol {
-    using C = typename Storage<T>::C;
-    using R = typename Storage<T>::R;
-    R rho, sig;         // rho, Sigma_in at plane k+1
+    using C = typename F::C;
+    using RU = typename F::RU;
+    using RR = std::conditional_t<F::IRS && !FIRST, C, RU>;
+    RR rho;             // rho (or 1/rho) at plane k+1
+    RU sig;             // Sigma_in at plane k+1
     C b;                // b at plane k (later sweeps)
-    R m[3];             // m at plane k+1 (FIRST)
-    R E;                // E at plane k+1 (first sweep that also forms the CFL maxima)
+    RU m[3];            // m at plane k+1 (FIRST)
+    RU E;               // E at plane k+1 (first sweep that also forms the CFL maxima)
 };
-template <class T, bool FIRST>
+template <class F, bool FIRST>
 struct SweepNb {
-    using R = typename Storage<T>::R;
-    R rho[4], sig[4];   // x/y neighbours of plane k
-    R m[4][3];          // (FIRST)
+    using RU = typename F::RU;
+    using RR = std::conditional_t<F::IRS && !FIRST, typename F::C, RU>;
+    RR rho[4];
+    RU sig[4];   // x/y neighbours of plane k
+    RU m[4][3];  // (FIRST)
 };
 
 #ifndef IGR_SWEEP_RY
@@ -317,19 +323,24 @@ constexpr int SWEEP_RY_FIRST = IGR_SWEEP_RY_FIRST;   // rows of a first-sweep bl
 // the expression of the standalone reduction, on the stored values); each
 // wave leaves its maximum in speed[blockIdx.x * RY + wave] and non-physical
 // states raise *flag, so the time step of the stage needs no separate pass.
-template <class T, bool FIRST, int RY, bool SPD = false>
-__global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, const T* Sin, T* Sout,
-                                                 typename Storage<T>::C* __restrict__ b,
-                                                 typename Storage<T>::C* __restrict__ irs, Geom g, int zc,
+// F: storage form; the state swept from is U (+ D with HASD, the split
+// form's stage difference).
+template <class F, bool FIRST, int RY, bool SPD = false, bool HASD = false>
+__global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __restrict__ U,
+                                                 const typename F::TD* __restrict__ D, const typename F::TS* Sin,
+                                                 typename F::TS* Sout, typename F::C* __restrict__ b,
+                                                 typename F::C* __restrict__ irs, Geom g, int zc,
                                                  int tiles_x, int tiles_y, int colour,
                                                  double* __restrict__ speed, int* __restrict__ flag) {
     static_assert(!SPD || FIRST, "the CFL maxima need the first sweep's state loads");
-    using S = Storage<T>;
-    using C = typename S::C;
+    using C = typename F::C;
+    using RU = typename F::RU;
+    using SS = Storage<typename F::TS>;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
-    // FP64: the first sweep stores 1/rho (interior and the face-ghost layer)
-    // and later sweeps read it instead of dividing again (same bytes as rho)
-    constexpr bool IRS = sizeof(C) == 8;
+    // the first sweep stores 1/rho (interior and the face-ghost layer) and
+    // later sweeps read it instead of dividing again (FP64: the same bytes
+    // as rho; split form: one FP32 value instead of a base and a difference)
+    constexpr bool IRS = F::IRS;
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
     // tiles are fetched once into that XCD's L2
@@ -363,62 +374,69 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
         if (k >= nz) return g.periodic[2] ? 0 : nz - 1;
         return k;
     };
-    auto load_col = [&](int k, SweepCol<T, FIRST>& P) {   // for iteration k
+    auto ldu = [&](long long o) { return F::template load_u<HASD>(U, D, o); };
+    auto getu = [&](long long o) { return F::cvt(ldu(o)); };
+    auto load_col = [&](int k, SweepCol<F, FIRST>& P) {   // for iteration k
         const long long op = zplane(k + 1);
         if constexpr (IRS && !FIRST)
             P.rho = irs[op];
         else
-            P.rho = S::load_raw(U + op);
-        P.sig = S::load_raw(Sin + col + (long long)(zsig(k + 1) + G) * sz);
-        if (FIRST) {
+            P.rho = ldu(op);
+        P.sig = F::load_s(Sin, col + (long long)(zsig(k + 1) + G) * sz);
+        if constexpr (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) P.m[c] = S::load_raw(U + (1 + c) * fs + op);
+            for (int c = 0; c < 3; ++c) P.m[c] = ldu((1 + c) * fs + op);
         } else {
             P.b = b[zplane(k)];
         }
-        if constexpr (SPD) P.E = S::load_raw(U + 4 * fs + op);
+        if constexpr (SPD) P.E = ldu(4 * fs + op);
     };
-    auto load_nb = [&](int k, SweepNb<T, FIRST>& P) {
+    auto load_nb = [&](int k, SweepNb<F, FIRST>& P) {
         const long long o = zplane(k);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             if constexpr (IRS && !FIRST)
                 P.rho[n] = irs[o + onb[n]];
             else
-                P.rho[n] = S::load_raw(U + o + onb[n]);
-            P.sig[n] = S::load_raw(Sin + o + osg[n]);
+                P.rho[n] = ldu(o + onb[n]);
+            P.sig[n] = F::load_s(Sin, o + osg[n]);
         }
-        if (FIRST) {
+        if constexpr (FIRST) {
 #pragma unroll
             for (int n = 0; n < 4; ++n)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) P.m[n][c] = S::load_raw(U + (1 + c) * fs + o + onb[n]);
+                for (int c = 0; c < 3; ++c) P.m[n][c] = ldu((1 + c) * fs + o + onb[n]);
         }
     };
-    using R = typename S::R;
-    // v: rho (register form), or 1/rho stored (FP64 later sweeps)
-    auto inv_rho = [&](R v) {
+    // v: rho (register form), or 1/rho stored (later sweeps of an IRS form)
+    auto inv_rho = [&](auto v) -> C {
         if constexpr (IRS && !FIRST)
             return v;
         else
-            return fast_rcp(S::cvt(v));
+            return fast_rcp(F::cvt(v));
     };
-    C ir_m = (IRS && !FIRST) ? irs[zplane(z0 - 1)] : fast_rcp(S::load(U + zplane(z0 - 1)));
-    C ir_c = (IRS && !FIRST) ? irs[zplane(z0)] : fast_rcp(S::load(U + zplane(z0)));
-    C s_m = S::load(Sin + col + (long long)(zsig(z0 - 1) + G) * sz);
-    C s_c = S::load(Sin + zplane(z0));
+    C ir_m, ir_c;
+    if constexpr (IRS && !FIRST) {
+        ir_m = irs[zplane(z0 - 1)];
+        ir_c = irs[zplane(z0)];
+    } else {
+        ir_m = fast_rcp(getu(zplane(z0 - 1)));
+        ir_c = fast_rcp(getu(zplane(z0)));
+    }
+    C s_m = F::cvt(F::load_s(Sin, col + (long long)(zsig(z0 - 1) + G) * sz));
+    C s_c = F::cvt(F::load_s(Sin, zplane(z0)));
     C u_m[3], u_c[3];
-    if (FIRST) {
+    if constexpr (FIRST) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            u_m[c] = S::load(U + (1 + c) * fs + zplane(z0 - 1)) * ir_m;
-            u_c[c] = S::load(U + (1 + c) * fs + zplane(z0)) * ir_c;
+            u_m[c] = getu((1 + c) * fs + zplane(z0 - 1)) * ir_m;
+            u_c[c] = getu((1 + c) * fs + zplane(z0)) * ir_c;
         }
     }
     if constexpr (SPD) {   // plane z0; the loop adds plane k+1 < z1 at iteration k
         const long long o0 = zplane(z0);
-        smax = cfl_speed(g, double(S::load(U + o0)), double(S::load(U + fs + o0)), double(S::load(U + 2 * fs + o0)),
-                         double(S::load(U + 3 * fs + o0)), double(S::load(U + 4 * fs + o0)), bad);
+        smax = cfl_speed(g, double(getu(o0)), double(getu(fs + o0)), double(getu(2 * fs + o0)),
+                         double(getu(3 * fs + o0)), double(getu(4 * fs + o0)), bad);
     }
     // Loads are unconditional (planes clamped to the chunk) and issued in
     // the order they are needed -- the neighbours of the next plane first,
@@ -426,21 +444,21 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
     // complete in order: waiting for the neighbours must not wait for the
     // look-ahead.  The loop is unrolled over the register rotation so that
     // the rotation is renaming, not copies of pending loads.
-    SweepCol<T, FIRST> q[PD];   // own columns for iterations k .. k+PD-1
+    SweepCol<F, FIRST> q[PD];   // own columns for iterations k .. k+PD-1
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_col(min(z0 + d, z1 - 1), q[d]);
-    SweepNb<T, FIRST> cur, nxt;
+    SweepNb<F, FIRST> cur, nxt;
     load_nb(z0, cur);
 #pragma unroll 6
     for (int k = z0; k < z1; ++k) {
-        const SweepCol<T, FIRST> cc = q[0];
+        const SweepCol<F, FIRST> cc = q[0];
 #pragma unroll
         for (int d = 0; d < PD - 1; ++d) q[d] = q[d + 1];
         load_nb(min(k + 1, z1 - 1), nxt);
         load_col(min(k + PD, z1 - 1), q[PD - 1]);
         const long long o = zplane(k);
         const C ir_p = inv_rho(cc.rho);
-        const C s_p = S::cvt(cc.sig);
+        const C s_p = F::cvt(cc.sig);
         C irn[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) irn[n] = inv_rho(cur.rho[n]);
@@ -457,14 +475,14 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
         C u_p[3];
         if (FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) u_p[c] = S::cvt(cc.m[c]) * ir_p;
+            for (int c = 0; c < 3; ++c) u_p[c] = F::cvt(cc.m[c]) * ir_p;
             C Gm[3][3];
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const C sc = C(0.5) * C(g.ih[d]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    Gm[c][d] = (S::cvt(cur.m[2 * d + 1][c]) * irn[2 * d + 1] - S::cvt(cur.m[2 * d][c]) * irn[2 * d]) * sc;
+                    Gm[c][d] = (F::cvt(cur.m[2 * d + 1][c]) * irn[2 * d + 1] - F::cvt(cur.m[2 * d][c]) * irn[2 * d]) * sc;
             }
             const C scz = C(0.5) * C(g.ih[2]);
 #pragma unroll
@@ -481,18 +499,18 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const T* __restrict__ U, co
             bk = cc.b;
         }
         const C irv[6] = {irn[0], irn[1], irn[2], irn[3], ir_m, ir_p};
-        const C sgv[6] = {S::cvt(cur.sig[0]), S::cvt(cur.sig[1]), S::cvt(cur.sig[2]), S::cvt(cur.sig[3]), s_m, s_p};
+        const C sgv[6] = {F::cvt(cur.sig[0]), F::cvt(cur.sig[1]), F::cvt(cur.sig[2]), F::cvt(cur.sig[3]), s_m, s_p};
         // colour < 0: every cell (Jacobi, Sout != Sin); else only the cells
         // with (i + j + k) % 2 == colour, in place (red-black Gauss-Seidel:
         // with even periodic extents every neighbour read here has the
         // other colour, so no value this launch writes is read by it)
         if (colour < 0 || ((i + j + k) & 1) == colour)
-            S::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, ja));
+            SS::store(Sout + o, jacobi_point(bk, ir_c, irv, sgv, ja));
         if constexpr (SPD) {
             if (k + 1 < z1)
-                smax = fmax(smax, cfl_speed(g, double(S::cvt(cc.rho)), double(S::cvt(cc.m[0])),
-                                            double(S::cvt(cc.m[1])), double(S::cvt(cc.m[2])),
-                                            double(S::cvt(cc.E)), bad));
+                smax = fmax(smax, cfl_speed(g, double(F::cvt(cc.rho)), double(F::cvt(cc.m[0])),
+                                            double(F::cvt(cc.m[1])), double(F::cvt(cc.m[2])),
+                                            double(F::cvt(cc.E)), bad));
         }
         ir_m = ir_c;
         ir_c = ir_p;
@@ -556,21 +574,24 @@ constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
 #endif
 constexpr int PAIR_NR_FIRST = IGR_PAIR_NR_FIRST;   // rows per block of the first pass of a solve
 
-template <class T, bool FIRST>
+template <class F, bool FIRST>
 struct PairIn;
-template <class T>
-struct PairIn<T, false> {   // loads of one plane for one thread (register form R)
-    using C = typename Storage<T>::C;
-    using R = typename Storage<T>::R;
-    R s0, ir;       // own column: Sigma, rho (or 1/rho when stored)
+template <class F>
+struct PairIn<F, false> {   // loads of one plane for one thread (register form RU)
+    using C = typename F::C;
+    using RU = typename F::RU;
+    using RR = std::conditional_t<F::IRS, C, RU>;   // rho, or the stored 1/rho
+    RU s0;          // own column: Sigma
+    RR ir;          // own column: rho (or 1/rho when stored)
     C b;            // own column: b
-    R xs0, xir;     // the ring-2 row (rows 0 and NR-1; others: own column)
+    RU xs0;         // the ring-2 row (rows 0 and NR-1; others: own column)
+    RR xir;
 };
-template <class T>
-struct PairIn<T, true> {    // first pass of a solve: the state instead of b and 1/rho
-    using R = typename Storage<T>::R;
-    R s0, rho, m[3];
-    R xs0, xrho, xm[3];
+template <class F>
+struct PairIn<F, true> {    // first pass of a solve: the state instead of b and 1/rho
+    using RU = typename F::RU;
+    RU s0, rho, m[3];
+    RU xs0, xrho, xm[3];
 };
 
 // FIRST: the first pass of a solve, which also forms the source b (eq. 9's
@@ -578,15 +599,22 @@ struct PairIn<T, true> {    // first pass of a solve: the state instead of b and
 // cell from u = m/rho in LDS (x/y neighbours) and a register queue (z), and
 // stores b and, in FP64, 1/rho for the later passes -- the work of the
 // single first sweep fused into the pair.
-template <class T, int NR, bool FIRST>
-__global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restrict__ U, const T* __restrict__ Sin,
-                                                            T* __restrict__ Sout,
-                                                            typename Storage<T>::C* __restrict__ b,
-                                                            typename Storage<T>::C* __restrict__ irs, Geom g,
+// F: storage form; the state swept from is U (+ D with HASD, the split
+// form's stage difference).
+#ifndef IGR_SPLIT_FIRST_MINW
+#define IGR_SPLIT_FIRST_MINW 1
+#endif
+template <class F, int NR, bool FIRST, bool HASD = false>
+__global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SPLIT_FIRST_MINW : 1) void k_sweep_pair(const typename F::TB* __restrict__ U,
+                                                            const typename F::TD* __restrict__ D,
+                                                            const typename F::TS* __restrict__ Sin,
+                                                            typename F::TS* __restrict__ Sout,
+                                                            typename F::C* __restrict__ b,
+                                                            typename F::C* __restrict__ irs, Geom g,
                                                             int zc, int tiles_x, int tiles_y) {
-    using S = Storage<T>;
-    using C = typename S::C;
-    constexpr bool IRS = sizeof(C) == 8;   // 1/rho stored by the first pass (FP64)
+    using C = typename F::C;
+    using SS = Storage<typename F::TS>;
+    constexpr bool IRS = F::IRS;           // 1/rho stored by the first pass (FP64, split form)
     constexpr int PD = 2;                   // planes loaded ahead (= register slots)
     constexpr int W0 = 68;                  // input row: columns x0-2 .. x0+65
     constexpr int W1 = 66;                  // level-1 and b row: x0-1 .. x0+64
@@ -647,18 +675,19 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     const long long xsig = (long long)(src(gyx, ny, py, 0, ny - 1) + G) * sy + (src(gx, nx, px, 0, nx - 1) + G);
     const long long xir = (long long)(src(gyx, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
     // every lane issues the same loads at clamped planes
-    auto load = [&](int P, PairIn<T, FIRST>& q) {
+    auto ldu = [&](long long o) { return F::template load_u<HASD>(U, D, o); };
+    auto load = [&](int P, PairIn<F, FIRST>& q) {
         const long long os = (long long)(src(P, nz, pz, 0, nz - 1) + G) * sz;
         const long long oi = (long long)(src(P, nz, pz, -1, nz) + G) * sz;
-        q.s0 = S::load_raw(Sin + os + csig);
-        q.xs0 = S::load_raw(Sin + os + xsig);
+        q.s0 = F::load_s(Sin, os + csig);
+        q.xs0 = F::load_s(Sin, os + xsig);
         if constexpr (FIRST) {
-            q.rho = S::load_raw(U + oi + cir);
-            q.xrho = S::load_raw(U + oi + xir);
+            q.rho = ldu(oi + cir);
+            q.xrho = ldu(oi + xir);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                q.m[c] = S::load_raw(U + (1 + c) * fs + oi + cir);
-                q.xm[c] = S::load_raw(U + (1 + c) * fs + oi + xir);
+                q.m[c] = ldu((1 + c) * fs + oi + cir);
+                q.xm[c] = ldu((1 + c) * fs + oi + xir);
             }
         } else {
             q.b = b[os + csig];
@@ -666,17 +695,16 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
                 q.ir = irs[oi + cir];
                 q.xir = irs[oi + xir];
             } else {
-                q.ir = S::load_raw(U + oi + cir);
-                q.xir = S::load_raw(U + oi + xir);
+                q.ir = ldu(oi + cir);
+                q.xir = ldu(oi + xir);
             }
         }
     };
-    using R = typename S::R;
-    auto inv = [](R v) {
+    auto inv = [](auto v) -> C {
         if constexpr (IRS && !FIRST)
             return v;
         else
-            return fast_rcp(S::cvt(v));
+            return fast_rcp(F::cvt(v));
     };
 
     const bool xlo = !px && gx == 0, xhi = !px && gx == nx - 1;
@@ -694,16 +722,16 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
     C bprev = C(0);
     C uq[3][3] = {};                          // FIRST: u of the own column at planes P-2, P-1, P
 
-    auto iter = [&](int P, PairIn<T, FIRST>& slot) {
+    auto iter = [&](int P, PairIn<F, FIRST>& slot) {
         // publish plane P, then refill the slot with plane P+PD
         const int w4 = (P + 8) % 4, w3 = (P + 6) % 3;
         if constexpr (FIRST) {
             const C ir = inv(slot.rho);
             C u[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) u[c] = S::cvt(slot.m[c]) * ir;
+            for (int c = 0; c < 3; ++c) u[c] = F::cvt(slot.m[c]) * ir;
             if (act) {
-                ls0[w4][cy][cx] = S::cvt(slot.s0);
+                ls0[w4][cy][cx] = F::cvt(slot.s0);
                 lir[w4][cy][cx] = ir;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) lu[c][w3][cy][cx] = u[c];
@@ -716,19 +744,19 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
             }
             if (xrow) {
                 const C xi = inv(slot.xrho);
-                ls0[w4][xr][cx] = S::cvt(slot.xs0);
+                ls0[w4][xr][cx] = F::cvt(slot.xs0);
                 lir[w4][xr][cx] = xi;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) lu[c][w3][xr][cx] = S::cvt(slot.xm[c]) * xi;
+                for (int c = 0; c < 3; ++c) lu[c][w3][xr][cx] = F::cvt(slot.xm[c]) * xi;
             }
         } else {
             if (act) {
-                ls0[w4][cy][cx] = S::cvt(slot.s0);
+                ls0[w4][cy][cx] = F::cvt(slot.s0);
                 lir[w4][cy][cx] = inv(slot.ir);
             }
             if (hasb) lb[w3][ly][bxc] = slot.b;
             if (xrow) {
-                ls0[w4][xr][cx] = S::cvt(slot.xs0);
+                ls0[w4][xr][cx] = F::cvt(slot.xs0);
                 lir[w4][xr][cx] = inv(slot.xir);
             }
         }
@@ -798,7 +826,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
                               ylo ? sc : ls1[a2][ly - 1][bxc], yhi ? sc : ls1[a2][ly + 1][bxc],
                               (!pz && z2 == 0) ? sc : qs1[0], (!pz && z2 == nz - 1) ? sc : v1};
             const C v2 = jacobi_apply(bprev, kc, sgv, ja);
-            S::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
+            SS::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
         }
         kc = kn;
         bprev = bn;
@@ -806,7 +834,7 @@ __global__ __launch_bounds__(64 * (NR + 1)) void k_sweep_pair(const T* __restric
         qs1[1] = v1;
     };
 
-    PairIn<T, FIRST> pa, pb;
+    PairIn<F, FIRST> pa, pb;
     load(z0 - 2, pa);
     load(z0 - 1, pb);
     int P = z0 - 2;

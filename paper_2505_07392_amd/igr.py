@@ -21,7 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libigr.so")
 IGR_OK, IGR_EINVAL, IGR_ENOMEM, IGR_EHIP, IGR_ENONFINITE, IGR_EUNSUPPORTED = range(6)
 BC_KIND = {"periodic": 0, "extrap": 1}
 PRECISION = {"f64": (0, torch.float64), "f32": (1, torch.float32), "bf16": (2, torch.bfloat16),
-             "f16": (3, torch.float16)}
+             "f16": (3, torch.float16), "bf16d": (4, torch.float32)}
+# Sigma's element type where it differs from the state's: the split form
+# (FP32 state, bfloat16 stage differences and Sigma)
+SIGMA_DTYPE = {"bf16d": torch.bfloat16}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 
 
@@ -40,7 +43,8 @@ class BC(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("nsweeps", ctypes.c_int32), ("sigma_block", ctypes.c_int32), ("smoother", ctypes.c_int32)]
+                ("nsweeps", ctypes.c_int32), ("sigma_block", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("zeta", ctypes.c_double)]
 
 
 class IGRError(RuntimeError):
@@ -128,7 +132,7 @@ class Solver:
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, *, gamma: float = 1.4,
                  alpha: float = 0.0, faces: Sequence[str] = ("extrap",) * 6, jets: Iterable = (),
                  nsweeps: int = 5, precision: str = "f64", sigma_block: int = 0, order: int = 5,
-                 smoother: str = "jacobi", device=None):
+                 smoother: str = "jacobi", mu: float = 0.0, zeta: float = 0.0, device=None):
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {list(PRECISION)}")
         self.nx, self.ny, self.nz = nx, ny, nz
@@ -136,6 +140,7 @@ class Solver:
         self.gamma, self.alpha, self.nsweeps = gamma, alpha, nsweeps
         self.precision = precision
         self.dtype = PRECISION[precision][1]
+        self.sigma_dtype = SIGMA_DTYPE.get(precision, self.dtype)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.shape = (nz + 2 * G, ny + 2 * G, nx + 2 * G)
         jets = list(jets)
@@ -148,7 +153,8 @@ class Solver:
         if smoother not in SMOOTHER:
             raise ValueError(f"smoother must be one of {list(SMOOTHER)}")
         self.order, self.smoother = order, smoother
-        opts = Opts(PRECISION[precision][0], order, nsweeps, sigma_block, SMOOTHER[smoother])
+        self.mu, self.zeta = mu, zeta
+        opts = Opts(PRECISION[precision][0], order, nsweeps, sigma_block, SMOOTHER[smoother], mu, zeta)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().igr_init(ctypes.byref(Grid(nx, ny, nz, dx, dy, dz)), gamma, alpha, ctypes.byref(bc),
@@ -163,14 +169,16 @@ class Solver:
                       order: int = 5, smoother: str = "jacobi", device=None) -> "Solver":
         return cls(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha, faces=tuple(w.faces),
                    jets=w.jets, nsweeps=w.nsweeps if nsweeps is None else nsweeps, precision=precision,
-                   sigma_block=sigma_block, order=order, smoother=smoother, device=device)
+                   sigma_block=sigma_block, order=order, smoother=smoother, mu=getattr(w, "mu", 0.0),
+                   zeta=getattr(w, "zeta", 0.0), device=device)
 
     # -- memory ------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
         return torch.zeros((5,) + self.shape, dtype=self.dtype, device=self.device)
 
     def new_field(self) -> torch.Tensor:
-        return torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+        """A padded Sigma field (Sigma's element type)."""
+        return torch.zeros(self.shape, dtype=self.sigma_dtype, device=self.device)
 
     @staticmethod
     def interior(a: torch.Tensor) -> torch.Tensor:
@@ -184,13 +192,14 @@ class Solver:
 
     def field_from(self, S) -> torch.Tensor:
         out = self.new_field()
-        self.interior(out).copy_(torch.as_tensor(S).to(dtype=torch.float64).to(self.dtype))
+        self.interior(out).copy_(torch.as_tensor(S).to(dtype=torch.float64).to(self.sigma_dtype))
         return out
 
     def _validate(self, t: torch.Tensor, nfields: int, name: str):
         shape = ((nfields,) if nfields > 1 else ()) + self.shape
-        if tuple(t.shape) != shape or t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
-            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of shape {shape} on {self.device}, "
+        dtype = self.dtype if nfields > 1 else self.sigma_dtype
+        if tuple(t.shape) != shape or t.dtype != dtype or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {dtype} tensor of shape {shape} on {self.device}, "
                              f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
     def _stream(self):

@@ -79,6 +79,8 @@ class Workload:
     nsteps: Optional[int] = None
     dt_fixed: Optional[float] = None
     seed: Optional[int] = None
+    mu: float = 0.0                     # shear viscosity (0: the Euler system)
+    zeta: float = 0.0                   # bulk viscosity
 
     @property
     def cells(self) -> int:
@@ -251,6 +253,21 @@ def fill_multi_jet_state(w: Workload, out) -> None:
         chi = torch.as_tensor(chi_r[k], device=out.device)[:, None] * chi_x[None, :]   # [ny, nx]
         Uj = jet_state[torch.as_tensor(owner[k], device=out.device)].T[:, :, None]    # [5, ny, 1]
         out[:, k].copy_(((1.0 - chi)[None] * amb + chi[None] * Uj).to(out.dtype))
+
+
+def multi_jet_state_at(w: Workload, kk: Sequence[int], jj: Sequence[int], ii: Sequence[int]) -> np.ndarray:
+    """The multi-jet initial state (same definition as multi_jet's U) at the
+    cells kk x jj x ii (interior indices), as a float64 array
+    [5, len(kk), len(jj), len(ii)]: a block of a grid too large to build
+    whole on the host."""
+    owner, chi_r = _jet_blend(w.ny, w.nz, w.dx, w.jets)
+    kk, jj, ii = (np.asarray(a, dtype=np.int64) for a in (kk, jj, ii))
+    chi_x = _plug_profile(w.nx, w.dx, *w.plug)[ii]
+    chi = chi_r[kk[:, None], jj[None, :]][:, :, None] * chi_x[None, None, :]
+    amb = conserved(1.0, 0.0, 0.0, 0.0, 1.0).reshape(5, 1, 1, 1)
+    jet_state = np.stack([conserved(j.rho, j.ux, j.uy, j.uz, j.p) for j in w.jets])        # [J, 5]
+    Uj = np.moveaxis(jet_state[owner[kk[:, None], jj[None, :]]], -1, 0)[:, :, :, None]   # [5, K, J, 1]
+    return np.ascontiguousarray((1.0 - chi)[None] * amb + chi[None] * Uj)
 
 
 def gradient_jets(n: int = 128) -> Workload:

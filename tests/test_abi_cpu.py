@@ -56,7 +56,8 @@ def _init(grid, gamma, alpha, bc, opts):
     ("pair", igr.IGR_EINVAL), ("precision", igr.IGR_EINVAL), ("order", igr.IGR_EUNSUPPORTED),
     ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("sigma_block", igr.IGR_EINVAL),
     ("smoother", igr.IGR_EINVAL), ("rbgs_odd_periodic", igr.IGR_EUNSUPPORTED),
-    ("plane_too_large", igr.IGR_EINVAL),
+    ("plane_too_large", igr.IGR_EINVAL), ("split_march", igr.IGR_EUNSUPPORTED),
+    ("negative_mu", igr.IGR_EINVAL), ("viscous_bf16", igr.IGR_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_arguments(case, code):
     grid, bc, opts, gamma, alpha = _grid(), _bc(), igr.Opts(0, 5, 5, 0), 1.4, 0.01
@@ -88,6 +89,12 @@ def test_init_rejects_bad_arguments(case, code):
         opts = igr.Opts(0, 5, 5, 0, 1)
     elif case == "plane_too_large":
         grid = igr.Grid(50000, 50000, 1, 1e-4, 1e-4, 1e-4)   # padded x-y plane beyond 32-bit offsets
+    elif case == "split_march":
+        opts = igr.Opts(4, 5, 5, 3)   # the split form runs single or two-sweep passes only
+    elif case == "negative_mu":
+        opts = igr.Opts(0, 5, 5, 0, 0, -1e-3, 0.0)
+    elif case == "viscous_bf16":
+        opts = igr.Opts(2, 5, 5, 0, 0, 1e-3, 0.0)     # viscous terms: FP64 and FP32 only
     rc, h = _init(grid, gamma, alpha, bc, opts)
     assert rc == code
     assert h.value is None

@@ -1,0 +1,163 @@
+"""Oracle parity on the 512^3 multi-jet box in the launch configuration
+the multi-jet rates are measured with (FP64, 10 sweeps, alpha = 4 dx^2,
+two-sweep Sigma passes with a two-sweep first pass, flux z chunks at the
+64-plane cap): one igr_step of the whole box on the GPU, and the oracle's
+step on windows around sampled cells.
+
+One SSP-RK3 step of a cell depends on the state within 3 (3 + S + 1) = 42
+cells (three stages, each a flux stencil of 3 cells on Sigma solved with S
+sweeps from a source one cell wide; the Sigma warm start of each stage adds
+S cells per earlier stage, which stays inside the same bound).  A window of
+half-width R = 44 is the true grid wherever it lies inside the box; an axis
+whose window reaches a face of the box keeps that face (outflow, and the
+inflow discs on x-min), the other axes wrap, so every cell within 2 of the
+sample sees the same inputs as on the whole box.  Window inputs come from
+the input definition (`inputs.multi_jet_state_at`), the time step from the
+jet and ambient states.  Tolerance: 1e-12 of each field's maximum (the
+largest |value| of the field over the oracle's windows).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import igr_ref as ref
+from paper_2505_07392_amd import igr, inputs
+from gpu_common import TOL, banner
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+N = 512
+R = 44          # window half-width (>= 42, the step's dependency radius at S = 10)
+B = 2           # compared block: cells within B of the sample
+
+# (k, j, i) samples: a disc edge at the inflow face, two points of the jet
+# plugs' fronts, and a corner of three outflow faces (at rest)
+SAMPLES = [(64, 74, 1), (320, 190, 14), (192, 448, 8), (508, 3, 500)]
+
+
+def _workload():
+    w = inputs.multi_jet(n=N, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10,
+                         build_state=False)
+    w.alpha = 4.0 * w.dx * w.dx
+    return w
+
+
+def _dt(w):
+    """0.4 / max over the initial and inflow states of sum_d (|u_d| + c)/dx:
+    the jets' (|u_x| + c) / dx + 2 c / dx dominates the ambient's 3 c / dx."""
+    speeds = [3.0 * math.sqrt(w.gamma) / w.dx]
+    for j in w.jets:
+        c = math.sqrt(w.gamma * j.p / j.rho)
+        speeds.append((abs(j.ux) + c) / w.dx + 2.0 * c / w.dx)
+    return 0.4 / max(speeds)
+
+
+def _block(c, n):
+    """The compared cells along one axis: within B of the sample, inside the box."""
+    return np.arange(max(0, c - B), min(n - 1, c + B) + 1)
+
+
+def _axis_window(c, n):
+    """Index range of the window along one axis and whether it keeps the
+    box's faces (else it wraps)."""
+    if c - R < 0 or c + R > n - 1:
+        lo, hi = max(0, c - R), min(n - 1, c + R)
+        return np.arange(lo, hi + 1), False
+    return np.arange(c - R, c + R + 1), True
+
+
+@pytest.fixture(scope="module")
+def gpu_step():
+    w = _workload()
+    dt = _dt(w)
+    banner(f"multi-jet {N}^3 FP64: filling the state")
+    s = igr.Solver.from_workload(w, precision="f64")
+    assert s.sigma_block == 2
+    U = s.new_state()
+    inputs.fill_multi_jet_state(w, s.interior(U))
+    S = s.new_field()
+    G = igr.G
+
+    def blk(k, j, i):
+        kk, jj, ii = _block(k, w.nz), _block(j, w.ny), _block(i, w.nx)
+        sl = (slice(kk[0] + G, kk[-1] + G + 1), slice(jj[0] + G, jj[-1] + G + 1), slice(ii[0] + G, ii[-1] + G + 1))
+        return (kk, jj, ii), sl
+
+    # the initial state on the device is the input definition, bitwise
+    for k, j, i in SAMPLES:
+        idx, sl = blk(k, j, i)
+        assert np.array_equal(U[(slice(None),) + sl].cpu().numpy(), inputs.multi_jet_state_at(w, *idx))
+    banner(f"multi-jet {N}^3 FP64: one igr_step, dt = {dt:.6e}")
+    s.step(U, S, dt_fixed=dt)
+    out = {}
+    for k, j, i in SAMPLES:
+        _, sl = blk(k, j, i)
+        out[(k, j, i)] = (U[(slice(None),) + sl].cpu().numpy(), S[sl].cpu().numpy())
+    s.close()
+    del U, S
+    torch.cuda.empty_cache()
+    return w, dt, out
+
+
+def _oracle_window(w, dt, sample):
+    """The oracle's step on the window around `sample`: the compared block
+    of the new state and Sigma, the block's initial state, and the
+    window's largest |value| per field."""
+    k, j, i = sample
+    ks, kper = _axis_window(k, w.nz)
+    js, jper = _axis_window(j, w.ny)
+    is_, iper = _axis_window(i, w.nx)
+    U0 = inputs.multi_jet_state_at(w, ks, js, is_)
+    faces = []
+    for per in (iper, jper, kper):
+        faces += ["periodic", "periodic"] if per else ["extrap", "extrap"]
+    # jet discs on the x-min face, centres shifted to window coordinates;
+    # every disc is kept, so each column of the window is owned as on the box
+    patches = ()
+    if is_[0] == 0:
+        patches = tuple(ref.Patch(jt.yc - js[0] * w.dy, jt.zc - ks[0] * w.dz, jt.r, jt.rho, jt.ux, jt.uy, jt.uz,
+                                  jt.p, jt.width) for jt in w.jets)
+    prob = ref.Problem(len(is_), len(js), len(ks), w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha,
+                       faces=tuple(faces), patches=patches, nsweeps=w.nsweeps)
+    Uo, So = ref.rk3_step(prob, torch.from_numpy(U0), torch.zeros(prob.shape, dtype=torch.float64), dt)
+    Uo, So = Uo.numpy(), So.numpy()
+    # the compared block in window coordinates
+    blk = tuple(slice(int(np.searchsorted(a, bb[0])), int(np.searchsorted(a, bb[-1])) + 1)
+                for a, bb in ((ks, _block(k, w.nz)), (js, _block(j, w.ny)), (is_, _block(i, w.nx))))
+    wmax = np.concatenate([np.abs(Uo).reshape(5, -1).max(axis=1), [np.abs(So).max()]])
+    return Uo[(slice(None),) + blk], So[blk], U0[(slice(None),) + blk], wmax
+
+
+@pytest.fixture(scope="module")
+def oracle_windows(gpu_step):
+    """Oracle blocks of every sample, and each field's scale: its largest
+    |value| over all windows (they hold jet cores, plug fronts and the
+    inflow face, so this is the field's maximum on the box after the step)."""
+    w, dt, _ = gpu_step
+    out = {}
+    for sample in SAMPLES:
+        banner(f"multi-jet {N}^3: oracle window around {sample}")
+        out[sample] = _oracle_window(w, dt, sample)
+    scale = np.max([v[3] for v in out.values()], axis=0)
+    return out, scale
+
+
+@pytest.mark.parametrize("sample", SAMPLES)
+def test_multijet_512_step_window(gpu_step, oracle_windows, sample):
+    _, _, gpu = gpu_step
+    blocks, scale = oracle_windows
+    Uw, Sw, U0, _ = blocks[sample]
+    Ug, Sg = gpu[sample]
+    for f, (g, o) in enumerate(list(zip(Ug, Uw)) + [(Sg, Sw)]):
+        err = np.abs(g - o).max() / scale[f]
+        print(f"[gpu-case] {sample} field {f}: rel err {err:.2e} (field scale {scale[f]:.3e})", flush=True)
+        assert err <= TOL, (sample, f, err)
+    # the step moved the state here (the sample is not a resting cell)
+    if sample != SAMPLES[-1]:
+        assert np.abs(Uw - U0).max() > 1e-6

@@ -225,22 +225,25 @@ def test_step_cfl(case):
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
 
 
-@pytest.mark.parametrize("precision", ["f64", "f16"])
+@pytest.mark.parametrize("precision", ["f64", "f16", "bf16d"])
 def test_advance_equals_repeated_steps(case, precision):
     """igr_advance (CFL maxima fused into each step's last stage) gives the
-    states and time steps of the same number of igr_step calls."""
+    states and time steps of the same number of igr_step calls (the split
+    form: advance alternates between U and its other FP32 state and copies
+    back after an odd count, each igr_step copies back)."""
     name, w = case
     w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 14, amp=0.1, umax=0.3))
     banner(f"advance x4 vs step x4 {name} {precision}")
     s = igr.Solver.from_workload(w, precision=precision)
     U1, U2 = s.state_from(w.U), s.state_from(w.U)
     S1, S2 = s.field_from(_sigma0(w)), s.field_from(_sigma0(w))
-    dts = [s.step(U1, S1, cfl=0.5) for _ in range(4)]
-    dt_last = s.advance(U2, S2, 4, cfl=0.5)
+    nsteps = 3 if precision == "bf16d" else 4
+    dts = [s.step(U1, S1, cfl=0.5) for _ in range(nsteps)]
+    dt_last = s.advance(U2, S2, nsteps, cfl=0.5)
     # the two maxima are the same FP64 expression on the same stored values;
     # allow one rounding of dt in case the compiler contracts it differently
     assert abs(dt_last - dts[-1]) <= 1e-15 * dts[-1]
-    tol = 1e-14 if precision == "f64" else 2e-3     # a few units of the 16-bit storage
+    tol = {"f64": 1e-14, "bf16d": 1e-5}.get(precision, 2e-3)     # a few units of the storage
     a, b = to_host(s, U1).astype(np.float64), to_host(s, U2).astype(np.float64)
     d = rel_linf(b, a).max()
     print(f"  max rel diff advance vs steps: {d:.3e}", flush=True)
@@ -381,6 +384,27 @@ def test_uniform_state_is_stationary_bitwise(faces):
     sig = s.field_from(np.full((nz, ny, nx), 0.37))
     L = to_host(s, s.rhs(U, sig))
     assert np.count_nonzero(L) == 0
+
+
+@pytest.mark.parametrize("faces", [("periodic",) * 6, ("extrap",) * 6])
+def test_uniform_state_split_form_steps_bitwise(faces):
+    """The split form keeps a uniform state exactly: every stage difference
+    is dt L = 0 and U^(n+1) = U^n + 2/3 (0 + 0); two steps through
+    igr_advance (the second from the other FP32 state) and one igr_step."""
+    nx, ny, nz = 70, 9, 11
+    U0 = np.empty((5, nz, ny, nx))
+    for f, v in enumerate((0.9, 0.3, -0.4, 0.2, 3.1)):
+        U0[f] = v
+    w = inputs.Workload("uniform", nx, ny, nz, 0.1, 0.2, 0.3, U0, alpha=0.01, faces=faces, nsweeps=3)
+    banner(f"uniform state split form {faces[0]}")
+    s = igr.Solver.from_workload(w, precision="bf16d")
+    U = s.state_from(U0)
+    sig = s.field_from(np.full((nz, ny, nx), 0.375))
+    s.advance(U, sig, 2, dt_fixed=1e-3)
+    s.step(U, sig, dt_fixed=1e-3)
+    got = to_host(s, U)
+    want = U0.astype(np.float32).astype(np.float64)
+    assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("bad", ["negative_rho", "nan_energy"])

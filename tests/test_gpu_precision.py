@@ -1,15 +1,18 @@
 """Precision forms (FP32 state and arithmetic; FP16 or BF16 storage with
-FP32 arithmetic; FP64 dt and sums in all) against the FP64 oracle.
+FP32 arithmetic; the split form: FP32 state, BF16 stage differences and
+BF16 Sigma; FP64 dt and sums in all) against the FP64 oracle.
 
 Per-field relative L1 error, sum |g - o| / sum |o|, after a run with a
 fixed time step (the same dt for every form).  Bounds: 1e-5 for FP32 and
 3e-3 for 16-bit storage.  FP16 storage (11 significand bits, the paper's
-storage format) meets 3e-3; BF16 storage (8 significand bits) does not:
-rounding every stored RK stage value to 2^-9 relative accumulates to
-1-5 % in 20-30 steps on these workloads (the same numbers come out of a CPU
-emulation that rounds the oracle's stage values), so its test pins the
-measured level (<= 6e-2) instead of the target.  Identically-zero oracle
-fields are skipped.
+storage format) and the split form (every stage state a BF16 difference
+from the FP32 state, Sigma in BF16) meet 3e-3.  Storing whole stage states
+in BF16 (8 significand bits) does not: rounding every stored RK stage value
+to 2^-9 relative accumulates to 1-5 % in 20-30 steps on these workloads
+(the same numbers come out of a CPU emulation that rounds the oracle's
+stage values), so that form has a test of its own that guards the known
+miss at its measured level (<= 6e-2), not the 3e-3 bound.  Identically-zero
+oracle fields are skipped.
 """
 
 import numpy as np
@@ -26,7 +29,9 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16": 6e-2}
+BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16d": 3e-3}
+# whole-state BF16 storage misses 3e-3; this guards its measured level only
+BF16_KNOWN_MISS = 6e-2
 
 
 def rel_l1(got, want):
@@ -64,7 +69,7 @@ def box_reference():
 
 
 @pytest.mark.parametrize("sigma_block", [1, 2])
-@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16d"])
 def test_precision_periodic_box(box_reference, precision, sigma_block):
     w, dt, (Uo, So) = box_reference
     banner(f"precision {precision}: periodic box 48^3, 20 steps, sigma_block={sigma_block}")
@@ -72,6 +77,18 @@ def test_precision_periodic_box(box_reference, precision, sigma_block):
     err = rel_l1(np.concatenate([Ug, Sg[None]]), np.concatenate([Uo, So[None]]))
     print(f"[gpu-case] {precision} rel L1 (rho, mx, my, mz, E, Sigma) = {err}", flush=True)
     assert (err <= BOUND[precision]).all(), err
+
+
+@pytest.mark.parametrize("sigma_block", [1, 2])
+def test_whole_state_bf16_known_miss_periodic_box(box_reference, sigma_block):
+    """Whole-state BF16 storage misses the 3e-3 bound (see the module
+    docstring); this only guards against it getting worse."""
+    w, dt, (Uo, So) = box_reference
+    banner(f"whole-state bf16 (known miss): periodic box 48^3, 20 steps, sigma_block={sigma_block}")
+    Ug, Sg = _run_gpu(w, "bf16", dt, 20, sigma_block)
+    err = rel_l1(np.concatenate([Ug, Sg[None]]), np.concatenate([Uo, So[None]]))
+    print(f"[gpu-case] bf16 rel L1 (rho, mx, my, mz, E, Sigma) = {err}", flush=True)
+    assert (err <= BF16_KNOWN_MISS).all(), err
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +100,7 @@ def jet_reference():
 
 
 @pytest.mark.parametrize("sigma_block", [1, 2])
-@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16d"])
 def test_precision_jets(jet_reference, precision, sigma_block):
     w, dt, (Uo, So) = jet_reference
     banner(f"precision {precision}: Mach-3 jets 40^3, 30 steps, sigma_block={sigma_block}")
@@ -94,12 +111,23 @@ def test_precision_jets(jet_reference, precision, sigma_block):
     assert (err[keep] <= BOUND[precision]).all(), err
 
 
+@pytest.mark.parametrize("sigma_block", [1, 2])
+def test_whole_state_bf16_known_miss_jets(jet_reference, sigma_block):
+    w, dt, (Uo, So) = jet_reference
+    banner(f"whole-state bf16 (known miss): Mach-3 jets 40^3, 30 steps, sigma_block={sigma_block}")
+    Ug, Sg = _run_gpu(w, "bf16", dt, 30, sigma_block)
+    err = rel_l1(np.concatenate([Ug, Sg[None]]), np.concatenate([Uo, So[None]]))
+    keep = [i for i in range(6) if np.abs(np.concatenate([Uo, So[None]])[i]).sum() > 0]
+    print(f"[gpu-case] bf16 rel L1 (rho, mx, my, mz, E, Sigma) = {err}", flush=True)
+    assert (err[keep] <= BF16_KNOWN_MISS).all(), err
+
+
 def test_fp64_parity_of_reductions_in_all_forms():
     """dt and sums are FP64 reductions in every form: they equal the FP64
     oracle's values on the form's own (rounded) state."""
     w = inputs.periodic_box(n=32, seed=3)
     banner("FP64 reductions in f32/bf16 forms")
-    for precision in ("f32", "f16", "bf16"):
+    for precision in ("f32", "f16", "bf16", "bf16d"):
         s = igr.Solver.from_workload(w, precision=precision)
         U = s.state_from(w.U)
         Ur = to_host(s, U)                        # the stored (rounded) state, widened exactly
@@ -117,12 +145,15 @@ def test_fp64_parity_of_reductions_in_all_forms():
     ("f64", 16, 2), ("f64", 256, 2),
     ("f16", 256, 1), ("bf16", 256, 1), ("f16", 384, 2),
     ("f32", 248, 1), ("f32", 256, 2),
+    ("bf16d", 275, 1), ("bf16d", 276, 2),
 ])
 def test_default_pass_structure(precision, n, want):
     """sigma_block 0 resolves to two-sweep passes in FP64, and in the forms
     with FP32 arithmetic once one sweep's working set (padded elements x
-    (3 x storage bytes + 4)) exceeds 256 MiB: 254^3 x 16 B = 250 MiB stays
-    single, 262^3 x 16 B = 274 MiB pairs.  An explicit choice is kept."""
+    (2 x Sigma bytes + rho bytes + 4)) exceeds 256 MiB: 254^3 x 16 B =
+    250 MiB stays single, 262^3 x 16 B = 274 MiB pairs; the split form reads
+    the FP32 1/rho stored by the first sweep (12 B: 281^3 stays single,
+    282^3 pairs).  An explicit choice is kept."""
     banner(f"default pass structure {precision} {n}^3")
     s = igr.Solver(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, precision=precision)
     assert s.sigma_block == want
@@ -135,10 +166,10 @@ def test_default_pass_structure(precision, n, want):
 # one-step bound per form at full size, relative to each field's maximum:
 # the three stage values are rounded to storage once each (FP32: 2^-24,
 # FP16: 2^-11, BF16: 2^-8 relative), everything else is FP32 arithmetic
-STEP_BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16": 2e-2}
+STEP_BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16": 2e-2, "bf16d": 3e-3}
 
 
-@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16", "bf16d"])
 def test_full_size_form_step_sampled(precision):
     """The 256^3 periodic box in each form, one igr_advance step with a
     fixed dt (the call and launch configuration the throughput is measured
