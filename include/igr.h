@@ -145,8 +145,10 @@ typedef struct {
 typedef struct igr_ctx igr_ctx;
 
 /* Create a context for one grid on the current device.  gamma > 1,
- * alpha >= 0 (the paper takes alpha proportional to dx^2).  On success
- * *out owns the scratch memory; release it with igr_finalize. */
+ * alpha >= 0 (the paper takes alpha proportional to dx^2); a padded x-y
+ * plane, (nx+6)*(ny+6), below 2^29 elements (the kernels address a plane
+ * with 32-bit byte offsets), else IGR_EINVAL.  On success *out owns the
+ * scratch memory; release it with igr_finalize. */
 int igr_init(const igr_grid *grid, double gamma, double alpha, const igr_bc *bc,
              const igr_opts *opts, igr_ctx **out);
 
@@ -200,7 +202,8 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
  * expression as the standalone reduction, on the values as stored), so the
  * separate pass over U runs only before the first step; in IGR_F64 each
  * step's first Sigma sweep forms the maxima of U instead, when the solve
- * starts with a single sweep (else the separate pass runs).  If dt_last is not NULL the stream is synchronised, *dt_last
+ * starts with a single sweep or a two-sweep pass (else the separate pass
+ * runs).  If dt_last is not NULL the stream is synchronised, *dt_last
  * receives the last step's dt and the error flag is checked.
  * nsteps >= 0. */
 int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,

@@ -263,25 +263,49 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 #ifndef IGR_PAIR_ZC_MIN
 #define IGR_PAIR_ZC_MIN 8
 #endif
-template <class F, bool FIRST, bool HASD>
-int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* Sin,
-              typename F::TS* Sout, hipStream_t s) {
-    using C = typename F::C;
-    const Geom& g = c->g;
-    constexpr int NR = FIRST ? PAIR_NR_FIRST : PAIR_NR;
-    const int tiles_x = (g.n[0] + 63) / 64, tiles_y = (g.n[1] + NR - 3) / (NR - 2);
-    const long long tiles = (long long)tiles_x * tiles_y;
+// Launch shape of a two-sweep pass with NR rows per block.
+struct PairShape {
+    int tiles_x, tiles_y, zc;
+    long long blocks;
+};
+PairShape pair_shape(const Geom& g, int nr) {
+    PairShape sh;
+    sh.tiles_x = (g.n[0] + 63) / 64;
+    sh.tiles_y = (g.n[1] + nr - 3) / (nr - 2);
+    const long long tiles = (long long)sh.tiles_x * sh.tiles_y;
     long long zc = (tiles * g.n[2] + IGR_PAIR_BLOCKS - 1) / IGR_PAIR_BLOCKS;
     if (zc < IGR_PAIR_ZC_MIN) zc = IGR_PAIR_ZC_MIN;
     if (zc > 128) zc = 128;
     if (zc > g.n[2]) zc = g.n[2];
-    const long long blocks = tiles * ((g.n[2] + zc - 1) / zc);
-    if (blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
+    sh.zc = int(zc);
+    sh.blocks = tiles * ((g.n[2] + zc - 1) / zc);
+    return sh;
+}
+// CFL maxima left by a first two-sweep pass that forms them: one per wave.
+long long pair_speed_slots(const Geom& g) { return pair_shape(g, PAIR_NR_FIRST).blocks * (PAIR_NR_FIRST + 1); }
+
+// speed (FIRST, FP64 state without a difference; nullable): the pass also
+// leaves the CFL maxima of U there.
+template <class F, bool FIRST, bool HASD>
+int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* Sin,
+              typename F::TS* Sout, hipStream_t s, double* speed = nullptr) {
+    using C = typename F::C;
+    const Geom& g = c->g;
+    constexpr int NR = FIRST ? PAIR_NR_FIRST : PAIR_NR;
+    const PairShape sh = pair_shape(g, NR);
+    if (sh.blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
     C* b = static_cast<C*>(c->d_b);
     C* ir = static_cast<C*>(c->d_ir);
+    constexpr bool SPD_OK = FIRST && !HASD && sizeof(C) == 8;
     return launch(c, K_JACOBI, s, [&] {
-        k_sweep_pair<F, NR, FIRST, HASD><<<dim3(unsigned(blocks)), dim3(64, NR + 1), 0, s>>>(
-            U, D, Sin, Sout, b, ir, g, int(zc), tiles_x, tiles_y);
+        if (SPD_OK && speed) {
+            if constexpr (SPD_OK)
+                k_sweep_pair<F, NR, true, false, true><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
+                    U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
+        } else {
+            k_sweep_pair<F, NR, FIRST, HASD><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
+                U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y);
+        }
     });
 }
 
@@ -380,12 +404,35 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
 #ifndef IGR_FIRST_PAIR
 #define IGR_FIRST_PAIR 1
 #endif
-        if (IGR_FIRST_PAIR && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
+#ifndef IGR_SOURCE_PASS
+#define IGR_SOURCE_PASS 0
+#endif
+        if (IGR_SOURCE_PASS && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
+            // an even count: the source (and 1/rho, and in FP64 the CFL
+            // maxima when asked) in a streaming pass of its own, then pairs
+            constexpr bool SPD_OK = sizeof(C) == 8 && !HASD;
+            const bool spd = SPD_OK && speed != nullptr;
+            const SweepShape sh = sweep_shape(g, SRC_RY);
+            IGR_TRY(launch(c, K_SOURCE, s, [&] {
+                if (spd) {
+                    if constexpr (SPD_OK)
+                        k_source_z<F, false, true><<<dim3(unsigned(sh.blocks)), dim3(64, SRC_RY), 0, s>>>(
+                            U, D, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
+                } else {
+                    k_source_z<F, HASD, false><<<dim3(unsigned(sh.blocks)), dim3(64, SRC_RY), 0, s>>>(
+                        U, D, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, nullptr, nullptr);
+                }
+            }));
+            if (spd && nspeed) *nspeed = int(sh.blocks * SRC_RY);
+        } else if (IGR_FIRST_PAIR && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
             // an even count: the first two sweeps in one pass that also
             // forms the source, then pairs (an odd count keeps the single
             // first sweep, then pairs: measured faster than first pass +
             // pairs + a single sweep)
-            IGR_TRY((pair_pass<F, true, HASD>(c, U, D, src, dst, s)));
+            // FP64: the pass also forms the CFL maxima of U when asked
+            const bool spd = sizeof(C) == 8 && !HASD && speed != nullptr;
+            IGR_TRY((pair_pass<F, true, HASD>(c, U, D, src, dst, s, spd ? speed : nullptr)));
+            if (spd && nspeed) *nspeed = int(pair_speed_slots(c->g));
             swap();
             left -= 2;
         } else if (left > 0) {
@@ -490,6 +537,9 @@ struct FluxShapeOf<Split> {
     static constexpr int BLOCKS = IGR_FLUX_BLOCKS_SPLIT;
 };
 
+#ifndef IGR_FLUX_ZC_MAX
+#define IGR_FLUX_ZC_MAX 64
+#endif
 struct FluxLaunch {
     int tiles_x, tiles_y, zc, chunks;
     long long blocks() const { return (long long)tiles_x * tiles_y * chunks; }
@@ -503,7 +553,12 @@ FluxLaunch flux_launch(const Geom& g, int ty, int target_blocks) {
     // long chunks: every chunk re-reads five planes to prime its z queue
     long long zc = (tiles * g.n[2] + target_blocks - 1) / target_blocks;
     if (zc < 8) zc = 8;
-    if (zc > 64) zc = 64;
+    if (zc > IGR_FLUX_ZC_MAX) zc = IGR_FLUX_ZC_MAX;
+    // on large grids twice the chunk, when at least 16 rounds of 256
+    // blocks remain (fewer priming re-reads; 1024^3 FP64: 41.8 against
+    // 42.4 ms per launch, while at 512^3 the 9 rounds it leaves lose 10 %)
+    if (tiles * ((g.n[2] + 2 * IGR_FLUX_ZC_MAX - 1) / (2 * IGR_FLUX_ZC_MAX)) >= 16 * 256)
+        zc = 2 * IGR_FLUX_ZC_MAX;
     if (zc > g.n[2]) zc = g.n[2];
     L.zc = int(zc);
     L.chunks = (g.n[2] + L.zc - 1) / L.zc;
@@ -1165,7 +1220,8 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     g.n[0] = grid->nx;
     g.n[1] = grid->ny;
     g.n[2] = grid->nz;
-    if (px * py > 0x7fffffffLL) {
+    // kernels address a plane with 32-bit byte offsets (8-byte elements)
+    if (px * py > (1LL << 29) - 1) {
         delete c;
         return fail(IGR_EINVAL, "x-y plane too large");
     }
@@ -1221,6 +1277,9 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
                        : c->precision == IGR_F32_BF16D ? flux_blocks<Split>(c)
                                                        : flux_blocks<Plain<float>>(c);
         if (c->precision == IGR_F64 && sweep_speed_slots(c->g) > nb) nb = sweep_speed_slots(c->g);
+        if (c->precision == IGR_F64 && pair_speed_slots(c->g) > nb) nb = pair_speed_slots(c->g);
+        if (c->precision == IGR_F64 && sweep_shape(c->g, SRC_RY).blocks * SRC_RY > nb)
+            nb = sweep_shape(c->g, SRC_RY).blocks * SRC_RY;
         rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
     }
     if (!rc && !c->patches.empty()) {

@@ -76,6 +76,20 @@ struct Storage<f16> {
     __device__ __forceinline__ static C stored(C v) { return float(f16(v)); }
 };
 
+// Element `o` of the x-y plane that starts at `plane`: a uniform base (kept
+// in scalar registers) plus a 32-bit byte offset per lane, the addressing
+// that global loads and stores take as they are (igr_init keeps a padded
+// plane below 2^29 elements, so the byte offset of any element type here
+// fits 32 bits).
+template <class T>
+__device__ __forceinline__ const T* at_plane(const T* plane, uint32_t o) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + o * uint32_t(sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T* at_plane(T* plane, uint32_t o) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + o * uint32_t(sizeof(T)));
+}
+
 // Storage forms: how the kernels read a stage state and Sigma.  A kernel
 // reads a state value through load_u (base array plus, with HASD, a
 // difference array) and a Sigma value through load_s, keeps the register
@@ -105,6 +119,12 @@ struct Plain {
                                                     long long o) {
         return S::load_raw((f < 5 ? b + f * fs : s) + o);
     }
+    // the same from plane bases and an in-plane offset (at_plane)
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_up(const TB* bp, const TD*, uint32_t o) {
+        return S::load_raw(at_plane(bp, o));
+    }
+    __device__ __forceinline__ static RU load_sp(const TS* sp, uint32_t o) { return S::load_raw(at_plane(sp, o)); }
     __device__ __forceinline__ static C cvt(RU r) { return S::cvt(r); }
 };
 
@@ -151,6 +171,22 @@ struct Split {
             r.d = (f < 5 ? d + f * fs : s)[o].bits;
         else
             r.d = f < 5 ? 0u : uint32_t(s[o].bits);
+        return r;
+    }
+    template <bool HASD>
+    __device__ __forceinline__ static RU load_up(const float* bp, const bf16* dp, uint32_t o) {
+        RU r;
+        r.a = *at_plane(bp, o);
+        if constexpr (HASD)
+            r.d = at_plane(dp, o)->bits;
+        else
+            r.d = 0u;
+        return r;
+    }
+    __device__ __forceinline__ static RU load_sp(const bf16* sp, uint32_t o) {
+        RU r;
+        r.a = 0.0f;
+        r.d = at_plane(sp, o)->bits;
         return r;
     }
     __device__ __forceinline__ static C cvt(RU r) { return r.a + __uint_as_float(r.d << 16); }

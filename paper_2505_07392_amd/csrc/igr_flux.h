@@ -103,6 +103,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const bool col_load = own && i < nx + G && j < ny + G;
     const bool col_out = own && i < nx && j < ny;
     const long long col = (long long)(j + G) * sy + (i + G);
+    const uint32_t col32 = uint32_t(col);   // in-plane offset (at_plane)
+    // base of field f of array a at a plane: uniform
+    auto fplane = [&](auto* a, int f, int plane) { return a + ((long long)f * fs + (long long)(plane + G) * sz); };
 
     // register queue: planes k-2 .. k+3 of the six fields (index 0..5)
     C q[6][6];
@@ -126,10 +129,14 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     // prefetched values stay in the storage's register form RU until used
     // (a 16-bit value converted at its load would wait for that load)
     auto load_col = [&](int plane, RU (&v)[6]) {
-        const long long o = col + (long long)(plane + G) * sz;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) v[f] = F::template load_u<HASD>(U, D, f * fs + o);
-        v[5] = F::load_s(Sg, o);
+        for (int f = 0; f < 5; ++f) {
+            if constexpr (HASD)
+                v[f] = F::template load_up<true>(fplane(U, f, plane), fplane(D, f, plane), col32);
+            else
+                v[f] = F::template load_up<false>(fplane(U, f, plane), nullptr, col32);
+        }
+        v[5] = F::load_sp(fplane(Sg, 0, plane), col32);
     };
     // prime with planes z0-3 .. z0+1 (slot p holds plane z0-3+p) and keep
     // plane z0+2 in `nxt`; every iteration shifts, moves `nxt` into slot 5
@@ -184,8 +191,16 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         for (int s = 0; s < HY; ++s) {
             int f, cy;
             hy[s] = RU{};
-            if (y_slot(s, f, cy))
-                hy[s] = F::template load_field<HASD>(U, D, Sg, f, fs, zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
+            // the field of a y-halo row is uniform in the wave
+            if (y_slot(s, f, cy)) {
+                const uint32_t o = uint32_t((y0 + cy + G) * sy + (x0 + lane + G));
+                if (f == 5)
+                    hy[s] = F::load_sp(fplane(Sg, 0, plane), o);
+                else if constexpr (HASD)
+                    hy[s] = F::template load_up<true>(fplane(U, f, plane), fplane(D, f, plane), o);
+                else
+                    hy[s] = F::template load_up<false>(fplane(U, f, plane), nullptr, o);
+            }
         }
         int f, cx, cy;
         hx = RU{};
@@ -223,13 +238,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     unv[f] = F::cvt(un_next[f]);
             }
             if (col_out && k + 1 < z1) {
-                const long long o = col + (long long)(k + 1 + G) * sz;
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     if constexpr (F::SPLIT)
-                        un_next[f].d = D[f * fs + o].bits;
+                        un_next[f].d = at_plane(fplane(D, f, k + 1), col32)->bits;
                     else
-                        un_next[f] = F::template load_u<false>(Un, nullptr, f * fs + o);
+                        un_next[f] = F::template load_up<false>(fplane(Un, f, k + 1), nullptr, col32);
                 }
             }
         }
@@ -307,7 +321,6 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             __syncthreads();
             // C: divergence and stage update
             if (col_out) {
-                const long long o = col + (long long)(k + G) * sz;
                 double vs[5];
                 C L[5];
 #pragma unroll
@@ -320,7 +333,6 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                 }
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
-                    const long long of = f * fs + o;
                     C v;
                     if (MODE == MODE_RHS) {
                         v = L[f];
@@ -343,12 +355,12 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
                     } else {
                         v = unv[f] * (C(1) / C(3)) + (C(2) / C(3)) * (q[f][2] + dt * L[f]);
                     }
-                    SO::store(out + of, v);
+                    SO::store(at_plane(fplane(out, f, k), col32), v);
                     if (FUSE) vs[f] = double(SO::stored(v));
                 }
                 // last stage: the solved Sigma of this plane into the caller's
                 // buffer when the solve ended in the scratch copy
-                if (MODE == MODE_STAGE3 && sig_out != nullptr) SS::store(sig_out + o, q[5][2]);
+                if (MODE == MODE_STAGE3 && sig_out != nullptr) SS::store(at_plane(fplane(sig_out, 0, k), col32), q[5][2]);
                 // last stage: CFL speed of the new state as stored (for the
                 // next step's dt), when the caller asked for it
                 if (FUSE && speed != nullptr)

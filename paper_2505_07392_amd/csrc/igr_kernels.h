@@ -216,9 +216,24 @@ __device__ __forceinline__ C recon3_right(C c, C d, C e) {
     return (C(2) * c + C(5) * d - C(1) * e) * (C(1) / C(6));
 }
 
-// Square root of a sound speed: correctly rounded in FP64, the hardware
-// instruction (1 ulp) in FP32.
-__device__ __forceinline__ double face_sqrt(double x) { return sqrt(x); }
+// Square root of a sound speed.  FP64: the hardware reciprocal-square-root
+// estimate refined by two Goldschmidt steps (g -> sqrt(x), h -> 1/(2 sqrt(x))),
+// within about an ulp; the argument gamma p / rho is a positive normal
+// number for every state the kernels accept (others are flagged), so the
+// range scaling and special-value handling of the library square root are
+// left out.  FP32: the hardware instruction (1 ulp).
+__device__ __forceinline__ double face_sqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
 __device__ __forceinline__ float face_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // LLF (Rusanov) flux along axis d of eqs. (6)-(8) with tau = 0:

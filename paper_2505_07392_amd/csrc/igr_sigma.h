@@ -271,6 +271,134 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
     }
 }
 
+// The source b of eq. (9) (second-order central velocity gradients) and,
+// for the forms that store it, 1/rho (interior and face-ghost layer), in a
+// pass of their own ahead of two-sweep passes: a streaming kernel of few
+// registers.  A 64 x SRC_RY block of columns marches a z chunk; the own
+// column's rho and m (and with SPD E) come one plane ahead, the u of the
+// four x/y neighbours from memory (L1/L2: the neighbours' own loads), the z
+// neighbours from a register queue.  With SPD it also forms the CFL speed
+// (cfl_speed) of every cell it covers: one maximum per wave in
+// speed[blockIdx.x * SRC_RY + wave], non-physical states raise *flag.
+constexpr int SRC_RY = 4;
+
+template <class F, bool HASD, bool SPD>
+__global__ __launch_bounds__(64 * SRC_RY) void k_source_z(const typename F::TB* __restrict__ U,
+                                                      const typename F::TD* __restrict__ D,
+                                                      typename F::C* __restrict__ b,
+                                                      typename F::C* __restrict__ irs, Geom g, int zc, int tiles_x,
+                                                      int tiles_y, double* __restrict__ speed,
+                                                      int* __restrict__ flag) {
+    using C = typename F::C;
+    using RU = typename F::RU;
+    int bidx = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = bidx % tiles_x;
+    bidx /= tiles_x;
+    const int by = bidx % tiles_y;
+    const int bz = bidx / tiles_y;
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * SRC_RY + threadIdx.y;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int z0 = bz * zc;
+    double smax = 0.0;
+    bool bad = false;
+    if (i < nx && j < ny) {
+        const int z1 = min(z0 + zc, nz);
+        const long long fs = g.fs;
+        const int sy = g.st[1], sz = g.st[2];
+        const long long col = (long long)(j + G) * sy + (i + G);
+        auto zplane = [&](int k) { return col + (long long)(k + G) * sz; };
+        auto ldu = [&](long long o) { return F::template load_u<HASD>(U, D, o); };
+        auto getu = [&](long long o) { return F::cvt(ldu(o)); };
+        const C alpha = C(g.alpha);
+        const C scx = C(0.5) * C(g.ih[0]), scy = C(0.5) * C(g.ih[1]), scz = C(0.5) * C(g.ih[2]);
+        const int onb[4] = {-1, 1, -sy, sy};
+        // u and 1/rho of the own column at planes k-1, k (registers)
+        C ir_m = fast_rcp(getu(zplane(z0 - 1))), ir_c = fast_rcp(getu(zplane(z0)));
+        C u_m[3], u_c[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u_m[c] = getu((1 + c) * fs + zplane(z0 - 1)) * ir_m;
+            u_c[c] = getu((1 + c) * fs + zplane(z0)) * ir_c;
+        }
+        if constexpr (SPD) {
+            const long long o0 = zplane(z0);
+            smax = cfl_speed(g, double(getu(o0)), double(getu(fs + o0)), double(getu(2 * fs + o0)),
+                             double(getu(3 * fs + o0)), double(getu(4 * fs + o0)), bad);
+        }
+        // own column of plane k+1 loaded one iteration ahead
+        RU nr, nm[3], nE;
+        auto load_next = [&](int k) {
+            const long long o = zplane(min(k + 1, nz));   // plane nz is the face ghost
+            nr = ldu(o);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nm[c] = ldu((1 + c) * fs + o);
+            if constexpr (SPD) nE = ldu(4 * fs + o);
+        };
+        load_next(z0);
+        for (int k = z0; k < z1; ++k) {
+            const long long o = zplane(k);
+            // x/y neighbours of plane k (filled ghosts at the faces)
+            RU nbr[4], nbm[4][3];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                nbr[n] = ldu(o + onb[n]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nbm[n][c] = ldu((1 + c) * fs + o + onb[n]);
+            }
+            const RU cr = nr, cm0 = nm[0], cm1 = nm[1], cm2 = nm[2];
+            RU cE;
+            if constexpr (SPD) cE = nE;
+            if (k + 1 < z1) load_next(k + 1);
+            const C ir_p = fast_rcp(F::cvt(cr));
+            const C u_p[3] = {F::cvt(cm0) * ir_p, F::cvt(cm1) * ir_p, F::cvt(cm2) * ir_p};
+            C irn[4];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(F::cvt(nbr[n]));
+            C Gm[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Gm[c][0] = (F::cvt(nbm[1][c]) * irn[1] - F::cvt(nbm[0][c]) * irn[0]) * scx;
+                Gm[c][1] = (F::cvt(nbm[3][c]) * irn[3] - F::cvt(nbm[2][c]) * irn[2]) * scy;
+                Gm[c][2] = (u_p[c] - u_m[c]) * scz;
+            }
+            const C tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
+            C tr2 = C(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
+            b[o] = alpha * (tr2 + tr * tr);
+            if constexpr (F::IRS) {
+                irs[o] = ir_c;
+                if (i == 0) irs[o - 1] = irn[0];
+                if (i == nx - 1) irs[o + 1] = irn[1];
+                if (j == 0) irs[o - sy] = irn[2];
+                if (j == ny - 1) irs[o + sy] = irn[3];
+                if (k == 0) irs[o - sz] = ir_m;
+                if (k == nz - 1) irs[o + sz] = ir_p;
+            }
+            if constexpr (SPD) {
+                if (k + 1 < z1)
+                    smax = fmax(smax, cfl_speed(g, double(F::cvt(cr)), double(F::cvt(cm0)), double(F::cvt(cm1)),
+                                                double(F::cvt(cm2)), double(F::cvt(cE)), bad));
+            }
+            ir_m = ir_c;
+            ir_c = ir_p;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u_m[c] = u_c[c];
+                u_c[c] = u_p[c];
+            }
+        }
+    }
+    if constexpr (SPD) {
+        for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+        if (threadIdx.x == 0) speed[(long long)blockIdx.x * SRC_RY + threadIdx.y] = smax;
+        if (bad) flag[0] = 1;
+    }
+}
+
 // One Jacobi sweep per pass, z-marching: a 64 x SWEEP_RY block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
@@ -592,26 +720,34 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
     using RU = typename F::RU;
     RU s0, rho, m[3];
     RU xs0, xrho, xm[3];
+    RU E;                   // own column (a first pass that also forms the CFL maxima)
 };
 
 // FIRST: the first pass of a solve, which also forms the source b (eq. 9's
 // left side, second-order central velocity gradients) at every level-1
 // cell from u = m/rho in LDS (x/y neighbours) and a register queue (z), and
 // stores b and, in FP64, 1/rho for the later passes -- the work of the
-// single first sweep fused into the pair.
+// single first sweep fused into the pair.  With SPD (FIRST) it also loads
+// E and forms the CFL speed (cfl_speed, the standalone reduction's
+// expression) of every interior cell of its output tile and chunk; each
+// wave leaves its maximum in speed[blockIdx.x * (NR + 1) + wave] and
+// non-physical states raise *flag.
 // F: storage form; the state swept from is U (+ D with HASD, the split
 // form's stage difference).
 #ifndef IGR_SPLIT_FIRST_MINW
 #define IGR_SPLIT_FIRST_MINW 1
 #endif
-template <class F, int NR, bool FIRST, bool HASD = false>
+template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false>
 __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SPLIT_FIRST_MINW : 1) void k_sweep_pair(const typename F::TB* __restrict__ U,
                                                             const typename F::TD* __restrict__ D,
                                                             const typename F::TS* __restrict__ Sin,
                                                             typename F::TS* __restrict__ Sout,
                                                             typename F::C* __restrict__ b,
                                                             typename F::C* __restrict__ irs, Geom g,
-                                                            int zc, int tiles_x, int tiles_y) {
+                                                            int zc, int tiles_x, int tiles_y,
+                                                            double* __restrict__ speed = nullptr,
+                                                            int* __restrict__ flag = nullptr) {
+    static_assert(!SPD || FIRST, "the CFL maxima need the first pass's state loads");
     using C = typename F::C;
     using SS = Storage<typename F::TS>;
     constexpr bool IRS = F::IRS;           // 1/rho stored by the first pass (FP64, split form)
@@ -676,9 +812,19 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     const long long xir = (long long)(src(gyx, ny, py, -1, ny) + G) * sy + (src(gx, nx, px, -1, nx) + G);
     // every lane issues the same loads at clamped planes
     auto ldu = [&](long long o) { return F::template load_u<HASD>(U, D, o); };
+    // plane index of a load: wrap (periodic z) or clamp, without a division
+    // (P is within a few planes of the box)
+    auto zsrc = [&](int c, int lo, int hi) {
+        if (pz) {
+            while (c < 0) c += nz;
+            while (c >= nz) c -= nz;
+            return c;
+        }
+        return c < lo ? lo : (c > hi ? hi : c);
+    };
     auto load = [&](int P, PairIn<F, FIRST>& q) {
-        const long long os = (long long)(src(P, nz, pz, 0, nz - 1) + G) * sz;
-        const long long oi = (long long)(src(P, nz, pz, -1, nz) + G) * sz;
+        const long long os = (long long)(zsrc(P, 0, nz - 1) + G) * sz;
+        const long long oi = (long long)(zsrc(P, -1, nz) + G) * sz;
         q.s0 = F::load_s(Sin, os + csig);
         q.xs0 = F::load_s(Sin, os + xsig);
         if constexpr (FIRST) {
@@ -689,6 +835,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                 q.m[c] = ldu((1 + c) * fs + oi + cir);
                 q.xm[c] = ldu((1 + c) * fs + oi + xir);
             }
+            if constexpr (SPD) q.E = ldu(4 * fs + oi + cir);
         } else {
             q.b = b[os + csig];
             if constexpr (IRS) {
@@ -721,10 +868,16 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     JacCoef<C> kc = {C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
     C bprev = C(0);
     C uq[3][3] = {};                          // FIRST: u of the own column at planes P-2, P-1, P
+    double smax = 0.0;                        // SPD: CFL maximum of this thread's cells
+    bool bad = false;
 
-    auto iter = [&](int P, PairIn<F, FIRST>& slot) {
+    // Ring slots follow r = (P - (z0 - 2)) mod 12, a compile-time constant
+    // of each unrolled iteration: plane P goes to slot r mod 4 (Sigma, 1/rho)
+    // and r mod 3 (b, u); level 1 at plane P-1 to slot (r+1) mod 2.
+    auto iter = [&](int P, auto Rc, PairIn<F, FIRST>& slot) {
+        constexpr int r = decltype(Rc)::value;
         // publish plane P, then refill the slot with plane P+PD
-        const int w4 = (P + 8) % 4, w3 = (P + 6) % 3;
+        constexpr int w4 = r % 4, w3 = r % 3;
         if constexpr (FIRST) {
             const C ir = inv(slot.rho);
             C u[3];
@@ -749,6 +902,13 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
 #pragma unroll
                 for (int c = 0; c < 3; ++c) lu[c][w3][xr][cx] = F::cvt(slot.xm[c]) * xi;
             }
+            if constexpr (SPD) {
+                // every interior cell of the output tile, once per chunk plane
+                if (outp && P >= z0 && P < z1)
+                    smax = fmax(smax, cfl_speed(g, double(F::cvt(slot.rho)), double(F::cvt(slot.m[0])),
+                                                double(F::cvt(slot.m[1])), double(F::cvt(slot.m[2])),
+                                                double(F::cvt(slot.E)), bad));
+            }
         } else {
             if (act) {
                 ls0[w4][cy][cx] = F::cvt(slot.s0);
@@ -765,12 +925,12 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
         if (P < z0) return;
         C v1 = C(0);
         const int z = P - 1;
-        const int a4 = (P + 7) % 4;
+        constexpr int a4 = (r + 3) % 4;   // plane P-1
         // level 1 at plane P-1
         JacCoef<C> kn = kc;
         C bn = bprev;
         if (lev1) {
-            const int m4 = (P + 6) % 4;
+            constexpr int m4 = (r + 2) % 4;   // plane P-2
             const C sc = ls0[a4][cy][cx];
             const C irv[6] = {lir[a4][cy][cx - 1], lir[a4][cy][cx + 1], lir[a4][cy - 1][cx], lir[a4][cy + 1][cx],
                               lir[m4][cy][cx], lir[w4][cy][cx]};
@@ -780,7 +940,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
             kn = jacobi_coef(lir[a4][cy][cx], irv, ja);
             if constexpr (FIRST) {
                 // source at this cell, eq. (9) left side
-                const int a3 = (P + 5) % 3;
+                constexpr int a3 = (r + 2) % 3;   // plane P-1
                 C Gm[3][3];
                 const C scx = C(0.5) * C(g.ih[0]), scy = C(0.5) * C(g.ih[1]), scz = C(0.5) * C(g.ih[2]);
 #pragma unroll
@@ -811,16 +971,16 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                     }
                 }
             } else {
-                bn = lb[(P + 5) % 3][ly][bxc];
+                bn = lb[(r + 2) % 3][ly][bxc];
             }
             v1 = jacobi_apply(bn, kn, sgv, ja);
-            ls1[(P + 7) & 1][ly][bxc] = v1;
+            ls1[(r + 1) & 1][ly][bxc] = v1;
         }
         // level 2 (output) at plane P-2, with the coefficients and source
         // level 1 used there in the previous iteration
         if (outp && P >= z0 + 2) {
             const int z2 = P - 2;
-            const int a2 = (P + 6) & 1;
+            constexpr int a2 = r & 1;   // level 1 at plane P-2
             const C sc = qs1[1];
             const C sgv[6] = {xlo ? sc : ls1[a2][ly][lx], xhi ? sc : ls1[a2][ly][lx + 2],
                               ylo ? sc : ls1[a2][ly - 1][bxc], yhi ? sc : ls1[a2][ly + 1][bxc],
@@ -837,12 +997,38 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     PairIn<F, FIRST> pa, pb;
     load(z0 - 2, pa);
     load(z0 - 1, pb);
+    // planes z0-2 .. z1+1, unrolled by 12 (the ring sizes' common multiple)
+    // so that every ring slot is a constant; P is uniform, so the exit is
+    // taken by the whole block
     int P = z0 - 2;
-    for (; P + 1 <= z1 + 1; P += 2) {
-        iter(P, pa);
-        iter(P + 1, pb);
+    const int Pend = z1 + 1;
+    auto step = [&](auto Rc, PairIn<F, FIRST>& slot) {
+        if (P > Pend) return false;
+        iter(P, Rc, slot);
+        ++P;
+        return true;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    using I7 = std::integral_constant<int, 7>;
+    using I8 = std::integral_constant<int, 8>;
+    using I9 = std::integral_constant<int, 9>;
+    using I10 = std::integral_constant<int, 10>;
+    using I11 = std::integral_constant<int, 11>;
+    while (step(I0{}, pa) && step(I1{}, pb) && step(I2{}, pa) && step(I3{}, pb) && step(I4{}, pa) &&
+           step(I5{}, pb) && step(I6{}, pa) && step(I7{}, pb) && step(I8{}, pa) && step(I9{}, pb) &&
+           step(I10{}, pa) && step(I11{}, pb)) {
     }
-    if (P <= z1 + 1) iter(P, pa);
+    if constexpr (SPD) {
+        for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+        if (threadIdx.x == 0) speed[(long long)blockIdx.x * (NR + 1) + threadIdx.y] = smax;
+        if (bad) flag[0] = 1;
+    }
 }
 
 }  // namespace igr

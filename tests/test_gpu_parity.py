@@ -251,12 +251,12 @@ def test_advance_equals_repeated_steps(case, precision):
     assert rel_linf(to_host(s, S2).astype(np.float64), to_host(s, S1).astype(np.float64)).max() <= tol
 
 
-@pytest.mark.parametrize("nsweeps,smoother", [(5, "jacobi"), (4, "jacobi"), (1, "jacobi"), (3, "rbgs")])
+@pytest.mark.parametrize("nsweeps,smoother", [(5, "jacobi"), (4, "jacobi"), (10, "jacobi"), (1, "jacobi"),
+                                              (3, "rbgs")])
 def test_cfl_dt_of_a_step_equals_the_standalone_reduction(nsweeps, smoother):
-    """FP64 steps form the CFL maxima in the first sweep of the first Sigma
-    solve when that solve starts with a single sweep (odd counts, red-black)
-    and fall back to the separate pass otherwise (even counts start with a
-    two-sweep pass): the time step is bitwise the standalone one."""
+    """FP64 steps form the CFL maxima in the first pass of the first Sigma
+    solve: a single first sweep (odd counts, red-black) or a first two-sweep
+    pass (even counts): the time step is bitwise the standalone one."""
     w = _mixed_workload(20, 40, 10, 6, faces=("extrap", "extrap", "periodic", "periodic", "periodic", "periodic"))
     banner(f"cfl dt fused vs standalone nsweeps={nsweeps} {smoother}")
     s = igr.Solver.from_workload(w, nsweeps=nsweeps, smoother=smoother)
