@@ -404,27 +404,7 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
 #ifndef IGR_FIRST_PAIR
 #define IGR_FIRST_PAIR 1
 #endif
-#ifndef IGR_SOURCE_PASS
-#define IGR_SOURCE_PASS 0
-#endif
-        if (IGR_SOURCE_PASS && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
-            // an even count: the source (and 1/rho, and in FP64 the CFL
-            // maxima when asked) in a streaming pass of its own, then pairs
-            constexpr bool SPD_OK = sizeof(C) == 8 && !HASD;
-            const bool spd = SPD_OK && speed != nullptr;
-            const SweepShape sh = sweep_shape(g, SRC_RY);
-            IGR_TRY(launch(c, K_SOURCE, s, [&] {
-                if (spd) {
-                    if constexpr (SPD_OK)
-                        k_source_z<F, false, true><<<dim3(unsigned(sh.blocks)), dim3(64, SRC_RY), 0, s>>>(
-                            U, D, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
-                } else {
-                    k_source_z<F, HASD, false><<<dim3(unsigned(sh.blocks)), dim3(64, SRC_RY), 0, s>>>(
-                        U, D, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, nullptr, nullptr);
-                }
-            }));
-            if (spd && nspeed) *nspeed = int(sh.blocks * SRC_RY);
-        } else if (IGR_FIRST_PAIR && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
+        if (IGR_FIRST_PAIR && c->sigma_block == 2 && left >= 2 && left % 2 == 0) {
             // an even count: the first two sweeps in one pass that also
             // forms the source, then pairs (an odd count keeps the single
             // first sweep, then pairs: measured faster than first pass +
@@ -1278,8 +1258,6 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
                                                        : flux_blocks<Plain<float>>(c);
         if (c->precision == IGR_F64 && sweep_speed_slots(c->g) > nb) nb = sweep_speed_slots(c->g);
         if (c->precision == IGR_F64 && pair_speed_slots(c->g) > nb) nb = pair_speed_slots(c->g);
-        if (c->precision == IGR_F64 && sweep_shape(c->g, SRC_RY).blocks * SRC_RY > nb)
-            nb = sweep_shape(c->g, SRC_RY).blocks * SRC_RY;
         rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
     }
     if (!rc && !c->patches.empty()) {

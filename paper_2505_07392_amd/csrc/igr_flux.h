@@ -128,15 +128,21 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 
     // prefetched values stay in the storage's register form RU until used
     // (a 16-bit value converted at its load would wait for that load)
+    // Plane base + 32-bit offset addressing, except for the split form's
+    // later stages, whose base + difference loads it leaves with more live
+    // registers (spills)
+    constexpr bool PLANE_ADDR = !HASD;
     auto load_col = [&](int plane, RU (&v)[6]) {
+        if constexpr (PLANE_ADDR) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            if constexpr (HASD)
-                v[f] = F::template load_up<true>(fplane(U, f, plane), fplane(D, f, plane), col32);
-            else
-                v[f] = F::template load_up<false>(fplane(U, f, plane), nullptr, col32);
+            for (int f = 0; f < 5; ++f) v[f] = F::template load_up<false>(fplane(U, f, plane), nullptr, col32);
+            v[5] = F::load_sp(fplane(Sg, 0, plane), col32);
+        } else {
+            const long long o = col + (long long)(plane + G) * sz;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) v[f] = F::template load_u<HASD>(U, D, f * fs + o);
+            v[5] = F::load_s(Sg, o);
         }
-        v[5] = F::load_sp(fplane(Sg, 0, plane), col32);
     };
     // prime with planes z0-3 .. z0+1 (slot p holds plane z0-3+p) and keep
     // plane z0+2 in `nxt`; every iteration shifts, moves `nxt` into slot 5
@@ -193,13 +199,16 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             hy[s] = RU{};
             // the field of a y-halo row is uniform in the wave
             if (y_slot(s, f, cy)) {
-                const uint32_t o = uint32_t((y0 + cy + G) * sy + (x0 + lane + G));
-                if (f == 5)
-                    hy[s] = F::load_sp(fplane(Sg, 0, plane), o);
-                else if constexpr (HASD)
-                    hy[s] = F::template load_up<true>(fplane(U, f, plane), fplane(D, f, plane), o);
-                else
-                    hy[s] = F::template load_up<false>(fplane(U, f, plane), nullptr, o);
+                if constexpr (PLANE_ADDR) {
+                    const uint32_t o = uint32_t((y0 + cy + G) * sy + (x0 + lane + G));
+                    if (f == 5)
+                        hy[s] = F::load_sp(fplane(Sg, 0, plane), o);
+                    else
+                        hy[s] = F::template load_up<false>(fplane(U, f, plane), nullptr, o);
+                } else {
+                    hy[s] = F::template load_field<HASD>(U, D, Sg, f, fs,
+                                                         zo + (long long)(y0 + cy + G) * sy + (x0 + lane + G));
+                }
             }
         }
         int f, cx, cy;
@@ -241,7 +250,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     if constexpr (F::SPLIT)
-                        un_next[f].d = at_plane(fplane(D, f, k + 1), col32)->bits;
+                        un_next[f].d = D[f * fs + col + (long long)(k + 1 + G) * sz].bits;
                     else
                         un_next[f] = F::template load_up<false>(fplane(Un, f, k + 1), nullptr, col32);
                 }

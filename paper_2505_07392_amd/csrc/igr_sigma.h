@@ -271,134 +271,6 @@ __global__ __launch_bounds__(SIG_TX* NR) void k_sigma_march(const T* __restrict_
     }
 }
 
-// The source b of eq. (9) (second-order central velocity gradients) and,
-// for the forms that store it, 1/rho (interior and face-ghost layer), in a
-// pass of their own ahead of two-sweep passes: a streaming kernel of few
-// registers.  A 64 x SRC_RY block of columns marches a z chunk; the own
-// column's rho and m (and with SPD E) come one plane ahead, the u of the
-// four x/y neighbours from memory (L1/L2: the neighbours' own loads), the z
-// neighbours from a register queue.  With SPD it also forms the CFL speed
-// (cfl_speed) of every cell it covers: one maximum per wave in
-// speed[blockIdx.x * SRC_RY + wave], non-physical states raise *flag.
-constexpr int SRC_RY = 4;
-
-template <class F, bool HASD, bool SPD>
-__global__ __launch_bounds__(64 * SRC_RY) void k_source_z(const typename F::TB* __restrict__ U,
-                                                      const typename F::TD* __restrict__ D,
-                                                      typename F::C* __restrict__ b,
-                                                      typename F::C* __restrict__ irs, Geom g, int zc, int tiles_x,
-                                                      int tiles_y, double* __restrict__ speed,
-                                                      int* __restrict__ flag) {
-    using C = typename F::C;
-    using RU = typename F::RU;
-    int bidx = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = bidx % tiles_x;
-    bidx /= tiles_x;
-    const int by = bidx % tiles_y;
-    const int bz = bidx / tiles_y;
-    const int i = bx * 64 + threadIdx.x;
-    const int j = by * SRC_RY + threadIdx.y;
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int z0 = bz * zc;
-    double smax = 0.0;
-    bool bad = false;
-    if (i < nx && j < ny) {
-        const int z1 = min(z0 + zc, nz);
-        const long long fs = g.fs;
-        const int sy = g.st[1], sz = g.st[2];
-        const long long col = (long long)(j + G) * sy + (i + G);
-        auto zplane = [&](int k) { return col + (long long)(k + G) * sz; };
-        auto ldu = [&](long long o) { return F::template load_u<HASD>(U, D, o); };
-        auto getu = [&](long long o) { return F::cvt(ldu(o)); };
-        const C alpha = C(g.alpha);
-        const C scx = C(0.5) * C(g.ih[0]), scy = C(0.5) * C(g.ih[1]), scz = C(0.5) * C(g.ih[2]);
-        const int onb[4] = {-1, 1, -sy, sy};
-        // u and 1/rho of the own column at planes k-1, k (registers)
-        C ir_m = fast_rcp(getu(zplane(z0 - 1))), ir_c = fast_rcp(getu(zplane(z0)));
-        C u_m[3], u_c[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            u_m[c] = getu((1 + c) * fs + zplane(z0 - 1)) * ir_m;
-            u_c[c] = getu((1 + c) * fs + zplane(z0)) * ir_c;
-        }
-        if constexpr (SPD) {
-            const long long o0 = zplane(z0);
-            smax = cfl_speed(g, double(getu(o0)), double(getu(fs + o0)), double(getu(2 * fs + o0)),
-                             double(getu(3 * fs + o0)), double(getu(4 * fs + o0)), bad);
-        }
-        // own column of plane k+1 loaded one iteration ahead
-        RU nr, nm[3], nE;
-        auto load_next = [&](int k) {
-            const long long o = zplane(min(k + 1, nz));   // plane nz is the face ghost
-            nr = ldu(o);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) nm[c] = ldu((1 + c) * fs + o);
-            if constexpr (SPD) nE = ldu(4 * fs + o);
-        };
-        load_next(z0);
-        for (int k = z0; k < z1; ++k) {
-            const long long o = zplane(k);
-            // x/y neighbours of plane k (filled ghosts at the faces)
-            RU nbr[4], nbm[4][3];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                nbr[n] = ldu(o + onb[n]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) nbm[n][c] = ldu((1 + c) * fs + o + onb[n]);
-            }
-            const RU cr = nr, cm0 = nm[0], cm1 = nm[1], cm2 = nm[2];
-            RU cE;
-            if constexpr (SPD) cE = nE;
-            if (k + 1 < z1) load_next(k + 1);
-            const C ir_p = fast_rcp(F::cvt(cr));
-            const C u_p[3] = {F::cvt(cm0) * ir_p, F::cvt(cm1) * ir_p, F::cvt(cm2) * ir_p};
-            C irn[4];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) irn[n] = fast_rcp(F::cvt(nbr[n]));
-            C Gm[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Gm[c][0] = (F::cvt(nbm[1][c]) * irn[1] - F::cvt(nbm[0][c]) * irn[0]) * scx;
-                Gm[c][1] = (F::cvt(nbm[3][c]) * irn[3] - F::cvt(nbm[2][c]) * irn[2]) * scy;
-                Gm[c][2] = (u_p[c] - u_m[c]) * scz;
-            }
-            const C tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
-            C tr2 = C(0);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
-            b[o] = alpha * (tr2 + tr * tr);
-            if constexpr (F::IRS) {
-                irs[o] = ir_c;
-                if (i == 0) irs[o - 1] = irn[0];
-                if (i == nx - 1) irs[o + 1] = irn[1];
-                if (j == 0) irs[o - sy] = irn[2];
-                if (j == ny - 1) irs[o + sy] = irn[3];
-                if (k == 0) irs[o - sz] = ir_m;
-                if (k == nz - 1) irs[o + sz] = ir_p;
-            }
-            if constexpr (SPD) {
-                if (k + 1 < z1)
-                    smax = fmax(smax, cfl_speed(g, double(F::cvt(cr)), double(F::cvt(cm0)), double(F::cvt(cm1)),
-                                                double(F::cvt(cm2)), double(F::cvt(cE)), bad));
-            }
-            ir_m = ir_c;
-            ir_c = ir_p;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                u_m[c] = u_c[c];
-                u_c[c] = u_p[c];
-            }
-        }
-    }
-    if constexpr (SPD) {
-        for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
-        if (threadIdx.x == 0) speed[(long long)blockIdx.x * SRC_RY + threadIdx.y] = smax;
-        if (bad) flag[0] = 1;
-    }
-}
-
 // One Jacobi sweep per pass, z-marching: a 64 x SWEEP_RY block of columns walks a
 // chunk of z planes, keeping the z neighbours of Sigma and 1/rho in
 // registers; x/y neighbours are read from memory (L1/L2 hits: adjacent
