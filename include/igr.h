@@ -166,8 +166,10 @@ int igr_field_size(const igr_ctx *ctx, int64_t *elems, int32_t *elem_bytes);
 int igr_get_opts(const igr_ctx *ctx, igr_opts *out);
 
 /* Replace the primitive state (rho, ux, uy, uz, p) of inflow disc `index`
- * (geometry unchanged).  Takes effect for later calls. */
-int igr_set_patch_state(igr_ctx *ctx, int32_t index, const double prim[5]);
+ * (geometry unchanged).  The update is enqueued on `stream`: work queued
+ * before it on that stream uses the old state, work queued after it the
+ * new one (other streams order themselves with events).  Asynchronous. */
+int igr_set_patch_state(igr_ctx *ctx, int32_t index, const double prim[5], void *stream);
 
 /* Entropic pressure: fill U's ghosts, form the source
  * b = alpha [tr((grad u)^2) + tr^2(grad u)] with central differences, and

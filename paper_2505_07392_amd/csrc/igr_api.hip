@@ -250,8 +250,8 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
     return sigma_pass<T, 1>(c, U, Sin, Sout, s);
 }
 
-// Launch of the two-sweep pass: 64 x (PAIR_NR-2) output tiles, z chunks
-// sized for about IGR_PAIR_BLOCKS blocks of 64 x (PAIR_NR+1) threads.
+// Launch of the two-sweep pass: 64 x (NR-2) output tiles, z chunks sized
+// for about IGR_PAIR_BLOCKS blocks of 64 x (NR+1) threads.
 // Last-level (Infinity) cache of one MI355X, bytes.
 #ifndef IGR_LLC_BYTES
 #define IGR_LLC_BYTES (256.0 * 1024 * 1024)
@@ -291,7 +291,7 @@ int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, cons
               typename F::TS* Sout, hipStream_t s, double* speed = nullptr) {
     using C = typename F::C;
     const Geom& g = c->g;
-    constexpr int NR = FIRST ? PAIR_NR_FIRST : PAIR_NR;
+    constexpr int NR = FIRST ? PAIR_NR_FIRST : pair_nr_later<F>();
     const PairShape sh = pair_shape(g, NR);
     if (sh.blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
     C* b = static_cast<C*>(c->d_b);
@@ -1090,6 +1090,17 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
+// Conserved state of inflow disc q (stream-ordered update of the jet table).
+__global__ void k_set_jet(double* jet, int q, double r, double mx, double my, double mz, double E) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        jet[q * 5 + 0] = r;
+        jet[q * 5 + 1] = mx;
+        jet[q * 5 + 2] = my;
+        jet[q * 5 + 3] = mz;
+        jet[q * 5 + 4] = E;
+    }
+}
+
 __global__ void k_clear_flag(int* flag) {
     if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0;
 }
@@ -1317,7 +1328,7 @@ int igr_get_opts(const igr_ctx* ctx, igr_opts* out) {
     return IGR_OK;
 }
 
-int igr_set_patch_state(igr_ctx* ctx, int32_t index, const double prim[5]) {
+int igr_set_patch_state(igr_ctx* ctx, int32_t index, const double prim[5], void* stream) {
     if (!ctx || !prim) return fail(IGR_EINVAL, "null argument");
     if (index < 0 || index >= (int)ctx->patches.size()) return fail(IGR_EINVAL, "patch index out of range");
     if (!(prim[0] > 0) || !(prim[4] > 0)) return fail(IGR_EINVAL, "jet needs rho > 0 and p > 0");
@@ -1327,8 +1338,15 @@ int igr_set_patch_state(igr_ctx* ctx, int32_t index, const double prim[5]) {
     pa.uy = prim[2];
     pa.uz = prim[3];
     pa.p = prim[4];
-    IGR_HIP(hipDeviceSynchronize());  // no queued kernel may still read the old table
-    return upload_jets(ctx, nullptr, true);
+    // the new conserved state travels as kernel arguments, ordered on the
+    // stream like every other call (work queued before it still reads the
+    // old state; no host buffer has to outlive the call)
+    const double gm = ctx->g.gamma;
+    const double E = pa.p / (gm - 1.0) + 0.5 * pa.rho * (pa.ux * pa.ux + pa.uy * pa.uy + pa.uz * pa.uz);
+    hipStream_t s = as_stream(stream);
+    k_set_jet<<<1, 64, 0, s>>>(ctx->d_jet, index, pa.rho, pa.rho * pa.ux, pa.rho * pa.uy, pa.rho * pa.uz, E);
+    IGR_HIP(hipGetLastError());
+    return IGR_OK;
 }
 
 int igr_sigma_solve(igr_ctx* ctx, void* U, void* sigma, int32_t nsweeps, double* resid_l2, void* stream) {

@@ -220,6 +220,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b % NX) * per + b / NX;
 }
 
+// Tile coordinates of a logical block index, x fastest: the blocks resident
+// on one XCD cover whole rows of tiles (long contiguous row segments per
+// plane).  A y-fastest order, which would let them share y-halo rows
+// through L2, measured slower (scattered 512-byte row pieces).
+__device__ __forceinline__ void tile_coords(int b, int tiles_x, int tiles_y, int& tx, int& ty, int& tz) {
+    tx = b % tiles_x;
+    b /= tiles_x;
+    ty = b % tiles_y;
+    tz = b / tiles_y;
+}
+
 // Padded-grid geometry passed by value to every kernel.
 struct Geom {
     int n[3];          // interior extents nx, ny, nz

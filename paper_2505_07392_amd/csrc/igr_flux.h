@@ -80,11 +80,8 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const int lane = threadIdx.x;
     const int wv = threadIdx.y;
     const int tid = wv * TX + lane;
-    int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = b % tiles_x;
-    b /= tiles_x;
-    const int ty = b % tiles_y;
-    const int cz = b / tiles_y;
+    int tx, ty, cz;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, tx, ty, cz);
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = cz * zc;

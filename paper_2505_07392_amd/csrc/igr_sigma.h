@@ -344,11 +344,8 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
     // tiles are fetched once into that XCD's L2
-    int bidx = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = bidx % tiles_x;
-    bidx /= tiles_x;
-    const int by = bidx % tiles_y;
-    const int bz = bidx / tiles_y;
+    int bx, by, bz;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * RY + threadIdx.y;
     const int z0 = bz * zc;
@@ -568,6 +565,16 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
 #define IGR_PAIR_NR 7
 #endif
 constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
+// FP64 later passes: 15 rows (16 waves, one block per CU: 117 VGPRs,
+// 111 KB of LDS) read (15 + 2) / 13 input rows per output row instead of
+// (7 + 2) / 5; the FP32-arithmetic forms keep 7 rows and several blocks per CU
+#ifndef IGR_PAIR_NR_F64
+#define IGR_PAIR_NR_F64 15
+#endif
+template <class F>
+constexpr int pair_nr_later() {
+    return std::is_same_v<typename F::C, double> ? IGR_PAIR_NR_F64 : PAIR_NR;
+}
 
 #ifndef IGR_PAIR_NR_FIRST
 #define IGR_PAIR_NR_FIRST 7
@@ -633,11 +640,8 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     __shared__ C ls1[2][NR][W1];
     static_assert(4 * NR - 4 <= 64, "side columns must fit one wave");
 
-    int bidx = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = bidx % tiles_x;
-    bidx /= tiles_x;
-    const int by = bidx % tiles_y;
-    const int bz = bidx / tiles_y;
+    int bx, by, bz;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int x0 = bx * 64, y0 = by * (NR - 2), z0 = bz * zc;
     const int z1 = min(z0 + zc, nz);

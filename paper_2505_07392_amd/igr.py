@@ -66,7 +66,8 @@ _SIGNATURES = {
     "igr_last_error": (ctypes.c_char_p, []),
     "igr_field_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "igr_get_opts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Opts)]),
-    "igr_set_patch_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "igr_set_patch_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_void_p]),
     "igr_sigma_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "igr_rhs": (ctypes.c_int, [ctypes.c_void_p] * 5),
@@ -290,7 +291,7 @@ class Solver:
 
     def set_jet_state(self, index: int, rho: float, ux: float, uy: float, uz: float, p: float):
         prim = (ctypes.c_double * 5)(rho, ux, uy, uz, p)
-        _check(lib().igr_set_patch_state(self._ctx, index, prim))
+        _check(lib().igr_set_patch_state(self._ctx, index, prim, self._stream()))
         self.jets[index] = [rho, ux, uy, uz, p]
 
     def timing(self, enable: bool):
@@ -307,12 +308,13 @@ class Solver:
         Returns (t, steps)."""
         t, n = 0.0, 0
         while t < t_end and n < max_steps:
-            dt = self.compute_dt(U, cfl)
+            dt = self.compute_dt(U, cfl)          # the one synchronising call per step
             if t + dt > t_end:
                 dt = t_end - t
-            self.step(U, sigma, dt_fixed=dt, sync=True)
+            self.step(U, sigma, dt_fixed=dt, sync=False)
             t += dt
             n += 1
+        self.check()
         return t, n
 
     def close(self):

@@ -356,6 +356,38 @@ def test_jets_steps_and_patch_update():
     assert rel_linf(to_host(s, L), Lw.numpy()).max() <= TOL
 
 
+
+def test_patch_update_is_stream_ordered():
+    """igr_set_patch_state is enqueued on the stream: steps queued before it
+    (not yet run) use the old jet state, steps after it the new one -- the
+    same bits as with a synchronisation around every call."""
+    w = inputs.multi_jet(n=32, jets_per_side=2, radius_cells=4.0, mach=3.0, nsweeps=10, nx=40)
+    banner("jets 40x32x32: patch update ordered on the stream")
+    s = igr.Solver.from_workload(w)
+    j = w.jets[0]
+    dt = 0.5 * s.compute_dt(s.state_from(w.U), 0.5)
+    outs = []
+    for sync in (True, False):
+        s.set_jet_state(0, j.rho, j.ux, j.uy, j.uz, j.p)
+        torch.cuda.synchronize()
+        U, sig = s.state_from(w.U), s.new_field()
+        for _ in range(3):
+            s.step(U, sig, dt_fixed=dt, sync=sync)
+        s.set_jet_state(0, 1.5 * j.rho, 0.8 * j.ux, j.uy, j.uz, 2.0 * j.p)
+        for _ in range(3):
+            s.step(U, sig, dt_fixed=dt, sync=sync)
+        s.check()
+        outs.append((to_host(s, U), to_host(s, sig)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    # and the new state reached the inflow face
+    prob = problem_from(w)
+    Uo, so = torch.from_numpy(w.U.copy()), torch.zeros(prob.shape, dtype=torch.float64)
+    for q in range(6):
+        if q == 3:
+            prob.patches[0].rho, prob.patches[0].ux, prob.patches[0].p = 1.5 * j.rho, 0.8 * j.ux, 2.0 * j.p
+        Uo, so = ref.rk3_step(prob, Uo, so, dt)
+    assert rel_linf(outs[1][0], Uo.numpy()).max() <= TOL
+
 def test_determinism_bitwise():
     w = _mixed_workload(70, 9, 7, 5)
     banner("determinism")
