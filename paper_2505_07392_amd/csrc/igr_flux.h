@@ -78,7 +78,9 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     __shared__ C fy[5][TY + 1][TX];
 
     const int lane = threadIdx.x;
-    const int wv = threadIdx.y;
+    // the wave index is uniform in the wave (blocks are 64 wide): SGPR
+    // arithmetic for everything that depends on the row only
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int tid = wv * TX + lane;
     int tx, ty, cz;
     tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, tx, ty, cz);
