@@ -581,6 +581,21 @@ constexpr int pair_nr_later() {
 #endif
 constexpr int PAIR_NR_FIRST = IGR_PAIR_NR_FIRST;   // rows per block of the first pass of a solve
 
+// Sigma neighbour of a cell: the LDS value, or the cell's own value `sc`
+// across a zero-gradient face.  With SEL the read is unconditional and the
+// choice a select; otherwise a branch skips the read.  (The LDS value comes
+// by pointer: through a reference the compiler would speculate the read
+// either way.)
+template <bool SEL, class C>
+__device__ __forceinline__ C face_or(bool face, C sc, const C* nb) {
+    if constexpr (SEL) {
+        const C t = *nb;
+        return face ? sc : t;
+    } else {
+        return face ? sc : *nb;
+    }
+}
+
 template <class F, bool FIRST>
 struct PairIn;
 template <class F>
@@ -639,6 +654,13 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     __shared__ C lu[FIRST ? 3 : 1][FIRST ? 3 : 1][FIRST ? NR + 2 : 1][FIRST ? W0 : 1];
     __shared__ C ls1[2][NR][W1];
     static_assert(4 * NR - 4 <= 64, "side columns must fit one wave");
+#ifndef IGR_PAIR_NBSEL
+#define IGR_PAIR_NBSEL 1
+#endif
+    // neighbour reads as selects in the FP32-arithmetic kernels (not in the
+    // split form's first pass of a later stage, where they would cost it a
+    // wave per SIMD: 129 VGPRs)
+    constexpr bool NBSEL = IGR_PAIR_NBSEL && sizeof(C) == 4 && !(FIRST && HASD);
 
     int bx, by, bz;
     tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
@@ -802,17 +824,24 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
         C v1 = C(0);
         const int z = P - 1;
         constexpr int a4 = (r + 3) % 4;   // plane P-1
-        // level 1 at plane P-1
-        JacCoef<C> kn = kc;
-        C bn = bprev;
-        if (lev1) {
+        // level 1 at plane P-1.  Every lane evaluates it (all its LDS reads
+        // are in bounds: rows 0..NR+1, columns 0..67 of the rings); lanes
+        // that form no level-1 cell discard the result and only lev1 lanes
+        // publish it.  Without a branch here the carried coefficients and
+        // values need no per-lane merge (register moves) each plane.
+        JacCoef<C> kn;
+        C bn;
+        {
             constexpr int m4 = (r + 2) % 4;   // plane P-2
             const C sc = ls0[a4][cy][cx];
             const C irv[6] = {lir[a4][cy][cx - 1], lir[a4][cy][cx + 1], lir[a4][cy - 1][cx], lir[a4][cy + 1][cx],
                               lir[m4][cy][cx], lir[w4][cy][cx]};
-            const C sgv[6] = {xlo ? sc : ls0[a4][cy][cx - 1], xhi ? sc : ls0[a4][cy][cx + 1],
-                              ylo ? sc : ls0[a4][cy - 1][cx], yhi ? sc : ls0[a4][cy + 1][cx],
-                              (!pz && z == 0) ? sc : ls0[m4][cy][cx], (!pz && z == nz - 1) ? sc : ls0[w4][cy][cx]};
+            const C sgv[6] = {face_or<NBSEL>(xlo, sc, &ls0[a4][cy][cx - 1]),
+                              face_or<NBSEL>(xhi, sc, &ls0[a4][cy][cx + 1]),
+                              face_or<NBSEL>(ylo, sc, &ls0[a4][cy - 1][cx]),
+                              face_or<NBSEL>(yhi, sc, &ls0[a4][cy + 1][cx]),
+                              face_or<NBSEL>(!pz && z == 0, sc, &ls0[m4][cy][cx]),
+                              face_or<NBSEL>(!pz && z == nz - 1, sc, &ls0[w4][cy][cx])};
             kn = jacobi_coef(lir[a4][cy][cx], irv, ja);
             if constexpr (FIRST) {
                 // source at this cell, eq. (9) left side
@@ -850,7 +879,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                 bn = lb[(r + 2) % 3][ly][bxc];
             }
             v1 = jacobi_apply(bn, kn, sgv, ja);
-            ls1[(r + 1) & 1][ly][bxc] = v1;
+            if (lev1) ls1[(r + 1) & 1][ly][bxc] = v1;
         }
         // level 2 (output) at plane P-2, with the coefficients and source
         // level 1 used there in the previous iteration
@@ -858,8 +887,10 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
             const int z2 = P - 2;
             constexpr int a2 = r & 1;   // level 1 at plane P-2
             const C sc = qs1[1];
-            const C sgv[6] = {xlo ? sc : ls1[a2][ly][lx], xhi ? sc : ls1[a2][ly][lx + 2],
-                              ylo ? sc : ls1[a2][ly - 1][bxc], yhi ? sc : ls1[a2][ly + 1][bxc],
+            const C sgv[6] = {face_or<NBSEL>(xlo, sc, &ls1[a2][ly][lx]),
+                              face_or<NBSEL>(xhi, sc, &ls1[a2][ly][lx + 2]),
+                              face_or<NBSEL>(ylo, sc, &ls1[a2][ly - 1][bxc]),
+                              face_or<NBSEL>(yhi, sc, &ls1[a2][ly + 1][bxc]),
                               (!pz && z2 == 0) ? sc : qs1[0], (!pz && z2 == nz - 1) ? sc : v1};
             const C v2 = jacobi_apply(bprev, kc, sgv, ja);
             SS::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
