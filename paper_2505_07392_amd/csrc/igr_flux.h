@@ -104,7 +104,17 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     const long long col = (long long)(j + G) * sy + (i + G);
     const uint32_t col32 = uint32_t(col);   // in-plane offset (at_plane)
     // base of field f of array a at a plane: uniform
-    auto fplane = [&](auto* a, int f, int plane) { return a + ((long long)f * fs + (long long)(plane + G) * sz); };
+    // element offset of a plane.  In the FP32-arithmetic kernels without a
+    // stage difference the plane index goes through readfirstlane (it is
+    // uniform), so that the 64-bit product stays on the scalar unit; the
+    // FP64 and difference kernels keep it in a vector register (on the
+    // scalar unit their scalar registers overflow and spill)
+    constexpr bool ZUNI = sizeof(C) == 4 && !HASD;
+    auto zoff = [&](int plane) {
+        if constexpr (ZUNI) plane = __builtin_amdgcn_readfirstlane(plane);
+        return (long long)(plane + G) * sz;
+    };
+    auto fplane = [&](auto* a, int f, int plane) { return a + ((long long)f * fs + zoff(plane)); };
 
     // register queue: planes k-2 .. k+3 of the six fields (index 0..5)
     C q[6][6];
@@ -137,7 +147,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             for (int f = 0; f < 5; ++f) v[f] = F::template load_up<false>(fplane(U, f, plane), nullptr, col32);
             v[5] = F::load_sp(fplane(Sg, 0, plane), col32);
         } else {
-            const long long o = col + (long long)(plane + G) * sz;
+            const long long o = col + zoff(plane);
 #pragma unroll
             for (int f = 0; f < 5; ++f) v[f] = F::template load_u<HASD>(U, D, f * fs + o);
             v[5] = F::load_s(Sg, o);
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
         return gx >= -G && gx < nx + G && (y0 + cy) < ny + G;
     };
     auto load_halo = [&](int plane) {
-        const long long zo = (long long)(plane + G) * sz;
+        const long long zo = zoff(plane);
 #pragma unroll
         for (int s = 0; s < HY; ++s) {
             int f, cy;
@@ -249,7 +259,7 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     if constexpr (F::SPLIT)
-                        un_next[f].d = D[f * fs + col + (long long)(k + 1 + G) * sz].bits;
+                        un_next[f].d = D[f * fs + col + zoff(k + 1)].bits;
                     else
                         un_next[f] = F::template load_up<false>(fplane(Un, f, k + 1), nullptr, col32);
                 }

@@ -629,7 +629,7 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
 // F: storage form; the state swept from is U (+ D with HASD, the split
 // form's stage difference).
 #ifndef IGR_SPLIT_FIRST_MINW
-#define IGR_SPLIT_FIRST_MINW 1
+#define IGR_SPLIT_FIRST_MINW 4
 #endif
 template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false>
 __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SPLIT_FIRST_MINW : 1) void k_sweep_pair(const typename F::TB* __restrict__ U,
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     // neighbour reads as selects in the FP32-arithmetic kernels (not in the
     // split form's first pass of a later stage, where they would cost it a
     // wave per SIMD: 129 VGPRs)
-    constexpr bool NBSEL = IGR_PAIR_NBSEL && sizeof(C) == 4 && !(FIRST && HASD);
+    constexpr bool NBSEL = IGR_PAIR_NBSEL && sizeof(C) == 4 && !(FIRST && HASD && IGR_SPLIT_FIRST_MINW < 4);
 
     int bx, by, bz;
     tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
