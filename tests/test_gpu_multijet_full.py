@@ -1,7 +1,8 @@
-"""Oracle parity on the 512^3 multi-jet box in the launch configuration
-the multi-jet rates are measured with (FP64, 10 sweeps, alpha = 4 dx^2,
-two-sweep Sigma passes with a two-sweep first pass, flux z chunks at the
-64-plane cap): one igr_step of the whole box on the GPU, and the oracle's
+"""Oracle parity on the multi-jet boxes at full size, in the launch
+configuration the multi-jet rates are measured with (FP64, 10 sweeps,
+alpha = 4 dx^2, two-sweep Sigma passes with a two-sweep first pass, flux z
+chunks of 64 planes at 512^3 and 128 planes at 1024^3 -- the benchmark's
+own workload): one igr_step of the whole box on the GPU, and the oracle's
 step on windows around sampled cells.
 
 One SSP-RK3 step of a cell depends on the state within 3 (3 + S + 1) = 42
@@ -32,17 +33,18 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-N = 512
 R = 44          # window half-width (>= 42, the step's dependency radius at S = 10)
 B = 2           # compared block: cells within B of the sample
 
-# (k, j, i) samples: a disc edge at the inflow face, two points of the jet
-# plugs' fronts, and a corner of three outflow faces (at rest)
-SAMPLES = [(64, 74, 1), (320, 190, 14), (192, 448, 8), (508, 3, 500)]
+# (k, j, i) samples per box size: a disc edge at the inflow face (on a z
+# chunk boundary of the flux launch at 1024^3), two points of the jet plugs'
+# fronts, and a corner of three outflow faces (at rest)
+SAMPLES = {512: [(64, 74, 1), (320, 190, 14), (192, 448, 8), (508, 3, 500)],
+           1024: [(128, 138, 1), (640, 382, 14), (384, 896, 8), (1020, 3, 1020)]}
 
 
-def _workload():
-    w = inputs.multi_jet(n=N, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10,
+def _workload(n):
+    w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10,
                          build_state=False)
     w.alpha = 4.0 * w.dx * w.dx
     return w
@@ -72,9 +74,10 @@ def _axis_window(c, n):
     return np.arange(c - R, c + R + 1), True
 
 
-@pytest.fixture(scope="module")
-def gpu_step():
-    w = _workload()
+@pytest.fixture(scope="module", params=sorted(SAMPLES))
+def gpu_step(request):
+    N = request.param
+    w = _workload(N)
     dt = _dt(w)
     banner(f"multi-jet {N}^3 FP64: filling the state")
     s = igr.Solver.from_workload(w, precision="f64")
@@ -90,19 +93,19 @@ def gpu_step():
         return (kk, jj, ii), sl
 
     # the initial state on the device is the input definition, bitwise
-    for k, j, i in SAMPLES:
+    for k, j, i in SAMPLES[N]:
         idx, sl = blk(k, j, i)
         assert np.array_equal(U[(slice(None),) + sl].cpu().numpy(), inputs.multi_jet_state_at(w, *idx))
     banner(f"multi-jet {N}^3 FP64: one igr_step, dt = {dt:.6e}")
     s.step(U, S, dt_fixed=dt)
     out = {}
-    for k, j, i in SAMPLES:
+    for k, j, i in SAMPLES[N]:
         _, sl = blk(k, j, i)
         out[(k, j, i)] = (U[(slice(None),) + sl].cpu().numpy(), S[sl].cpu().numpy())
     s.close()
     del U, S
     torch.cuda.empty_cache()
-    return w, dt, out
+    return N, w, dt, out
 
 
 def _oracle_window(w, dt, sample):
@@ -139,18 +142,19 @@ def oracle_windows(gpu_step):
     """Oracle blocks of every sample, and each field's scale: its largest
     |value| over all windows (they hold jet cores, plug fronts and the
     inflow face, so this is the field's maximum on the box after the step)."""
-    w, dt, _ = gpu_step
+    N, w, dt, _ = gpu_step
     out = {}
-    for sample in SAMPLES:
+    for sample in SAMPLES[N]:
         banner(f"multi-jet {N}^3: oracle window around {sample}")
         out[sample] = _oracle_window(w, dt, sample)
     scale = np.max([v[3] for v in out.values()], axis=0)
     return out, scale
 
 
-@pytest.mark.parametrize("sample", SAMPLES)
-def test_multijet_512_step_window(gpu_step, oracle_windows, sample):
-    _, _, gpu = gpu_step
+@pytest.mark.parametrize("sample", range(4))
+def test_multijet_full_size_step_window(gpu_step, oracle_windows, sample):
+    N, _, _, gpu = gpu_step
+    sample = SAMPLES[N][sample]
     blocks, scale = oracle_windows
     Uw, Sw, U0, _ = blocks[sample]
     Ug, Sg = gpu[sample]
@@ -159,5 +163,5 @@ def test_multijet_512_step_window(gpu_step, oracle_windows, sample):
         print(f"[gpu-case] {sample} field {f}: rel err {err:.2e} (field scale {scale[f]:.3e})", flush=True)
         assert err <= TOL, (sample, f, err)
     # the step moved the state here (the sample is not a resting cell)
-    if sample != SAMPLES[-1]:
+    if sample != SAMPLES[N][-1]:
         assert np.abs(Uw - U0).max() > 1e-6
