@@ -291,17 +291,21 @@ int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, cons
               typename F::TS* Sout, hipStream_t s, double* speed = nullptr) {
     using C = typename F::C;
     const Geom& g = c->g;
-    constexpr int NR = FIRST ? PAIR_NR_FIRST : pair_nr_later<F>();
-    const PairShape sh = pair_shape(g, NR);
+    // rows per block: the first pass that also forms the CFL maxima keeps
+    // PAIR_NR_FIRST (its speed slots are sized by it)
+    constexpr int NR = FIRST ? pair_nr_first<F, HASD>() : pair_nr_later<F>();
+    constexpr bool SPD_OK = FIRST && !HASD && sizeof(C) == 8;
+    const bool spd = SPD_OK && speed != nullptr;
+    const PairShape sh = pair_shape(g, spd ? PAIR_NR_FIRST : NR);
     if (sh.blocks > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the sweep launch");
     C* b = static_cast<C*>(c->d_b);
     C* ir = static_cast<C*>(c->d_ir);
-    constexpr bool SPD_OK = FIRST && !HASD && sizeof(C) == 8;
     return launch(c, K_JACOBI, s, [&] {
-        if (SPD_OK && speed) {
+        if (spd) {
             if constexpr (SPD_OK)
-                k_sweep_pair<F, NR, true, false, true><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
-                    U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
+                k_sweep_pair<F, PAIR_NR_FIRST, true, false, true>
+                    <<<dim3(unsigned(sh.blocks)), dim3(64, PAIR_NR_FIRST + 1), 0, s>>>(
+                        U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
         } else {
             k_sweep_pair<F, NR, FIRST, HASD><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
                 U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y);

@@ -562,12 +562,13 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
 // zero-gradient face the missing Sigma neighbour is the cell itself.
 // The intermediate level stays in the arithmetic type (it is never stored).
 #ifndef IGR_PAIR_NR
-#define IGR_PAIR_NR 7
+#define IGR_PAIR_NR 11
 #endif
-constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2)
-// FP64 later passes: 15 rows (16 waves, one block per CU: 117 VGPRs,
-// 111 KB of LDS) read (15 + 2) / 13 input rows per output row instead of
-// (7 + 2) / 5; the FP32-arithmetic forms keep 7 rows and several blocks per CU
+constexpr int PAIR_NR = IGR_PAIR_NR;   // rows per pair block (output NR-2), FP32 arithmetic
+// Rows per block, measured at 1024^3: FP64 later passes 15 (16 waves, one
+// block per CU: 117 VGPRs, 111 KB of LDS; (15 + 2) / 13 input rows per
+// output row instead of (7 + 2) / 5); FP32-arithmetic later passes 11 (two
+// blocks of 12 waves per CU; 13 and 15 rows were slower)
 #ifndef IGR_PAIR_NR_F64
 #define IGR_PAIR_NR_F64 15
 #endif
@@ -580,6 +581,26 @@ constexpr int pair_nr_later() {
 #define IGR_PAIR_NR_FIRST 7
 #endif
 constexpr int PAIR_NR_FIRST = IGR_PAIR_NR_FIRST;   // rows per block of the first pass of a solve
+// First pass (without the CFL maxima): rows per block by arithmetic type,
+// measured at 1024^3: FP64 11 (12 waves at 168 VGPRs, 132 KB of LDS:
+// 21.4 -> 17.0 ms per launch against 7 rows; 13 rows spill), FP32 15
+// (9.2 -> 7.9 ms), the split form's first pass of a later stage 15 (13.3 ->
+// 12.2 ms).  The FP64 first pass that also forms the CFL maxima keeps
+// PAIR_NR_FIRST (213 VGPRs at 2 waves per SIMD).
+#ifndef IGR_PAIR_NR_FIRST_F64
+#define IGR_PAIR_NR_FIRST_F64 11
+#endif
+#ifndef IGR_PAIR_NR_FIRST_F32
+#define IGR_PAIR_NR_FIRST_F32 15
+#endif
+#ifndef IGR_PAIR_NR_FIRST_HASD
+#define IGR_PAIR_NR_FIRST_HASD 15
+#endif
+template <class F, bool HASD>
+constexpr int pair_nr_first() {
+    return std::is_same_v<typename F::C, double> ? IGR_PAIR_NR_FIRST_F64
+                                                 : (HASD ? IGR_PAIR_NR_FIRST_HASD : IGR_PAIR_NR_FIRST_F32);
+}
 
 // Sigma neighbour of a cell: the LDS value, or the cell's own value `sc`
 // across a zero-gradient face.  With SEL the read is unconditional and the
