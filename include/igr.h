@@ -202,10 +202,9 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
  * CFL time step (dt_fixed <= 0) the maximum speed for step n+1 is formed
  * by step n's last stage as it writes the new state (the same FP64
  * expression as the standalone reduction, on the values as stored), so the
- * separate pass over U runs only before the first step; in IGR_F64 each
- * step's first Sigma sweep forms the maxima of U instead, when the solve
- * starts with a single sweep or a two-sweep pass (else the separate pass
- * runs).  If dt_last is not NULL the stream is synchronised, *dt_last
+ * separate pass over U runs only before the first step (with viscous
+ * terms every step forms its maximum as igr_step does).  If dt_last is not
+ * NULL the stream is synchronised, *dt_last
  * receives the last step's dt and the error flag is checked.
  * nsteps >= 0. */
 int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,

@@ -738,20 +738,19 @@ int step_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, double cfl, do
     return settle_state<F>(c, Unew, U, s);
 }
 
-// nsteps steps.  With a CFL time step in the forms with FP32 arithmetic,
-// the first step's maximum comes from the standalone reduction and every
-// later one from the maxima that the previous step's last stage left in
-// d_speed (with viscous terms, which the last stage adds after the flux
-// kernel, every step runs the standalone reduction).  FP64 forms each step's maxima in its first sweep instead (the
-// FP64 flux kernel is at its register limit: fused there it spills).  The
-// split form alternates between the caller's U and its other FP32 state and
-// copies the last state into U if it ends in the other one.
+// nsteps steps.  With a CFL time step the first step's maximum comes from
+// the standalone reduction and every later one from the maxima that the
+// previous step's last stage left in d_speed (with viscous terms, which the
+// last stage adds after the flux kernel, every step forms its maxima the
+// way igr_step does).  The split form alternates between the caller's U and
+// its other FP32 state and copies the last state into U if it ends in the
+// other one.
 template <class F>
 int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int nsteps, double cfl, double dt_fixed,
                  hipStream_t s) {
     using TB = typename F::TB;
     const bool use_cfl = !(dt_fixed > 0.0);
-    const bool fused = sizeof(typename F::C) == 4 && !c->viscous;
+    const bool fused = !c->viscous;
     const int nblk = int(flux_blocks<F>(c));
     TB* U = Ucaller;
     for (int n = 0; n < nsteps; ++n) {

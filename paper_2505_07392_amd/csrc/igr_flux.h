@@ -120,10 +120,10 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     C q[6][6];
     C Fz_prev[5];
     bool bad = false;
-    // fused CFL maximum of the last stage (FP32 arithmetic only: the FP64
-    // kernel is at its register limit): one LDS slot per thread, since a
-    // register carried through the plane loop would raise its peak
-    constexpr bool FUSE = MODE == MODE_STAGE3 && sizeof(C) == 4;
+    // fused CFL maximum of the last stage: one LDS slot per thread, since a
+    // register carried through the plane loop would raise its peak (FP64
+    // stage 3: 251 VGPRs, no spill)
+    constexpr bool FUSE = MODE == MODE_STAGE3;
     __shared__ double smax[FUSE ? FLUX_TX * (TY + 1) : 1];
     if (FUSE) smax[tid] = 0.0;
     // columns that are never loaded keep a valid state (their faces are

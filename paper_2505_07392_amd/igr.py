@@ -238,10 +238,9 @@ class Solver:
 
     def advance(self, U: torch.Tensor, sigma: torch.Tensor, nsteps: int, cfl: float = 0.5, dt_fixed: float = 0.0,
                 sync: bool = True) -> Optional[float]:
-        """nsteps SSP-RK3 steps in place (in the FP32-arithmetic forms each
-        later step's CFL maximum is fused into the previous step's last
-        stage; FP64 runs the separate reduction every step); returns the
-        last dt (and checks the non-finite flag) when sync is True."""
+        """nsteps SSP-RK3 steps in place (each later step's CFL maximum is
+        fused into the previous step's last stage); returns the last dt (and
+        checks the non-finite flag) when sync is True."""
         self._validate(U, 5, "U")
         self._validate(sigma, 1, "sigma")
         dt = ctypes.c_double(0.0)
