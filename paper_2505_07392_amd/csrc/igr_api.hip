@@ -263,6 +263,9 @@ int sigma_pass_k(igr_ctx* c, int k, const T* U, const T* Sin, T* Sout, hipStream
 #ifndef IGR_PAIR_ZC_MIN
 #define IGR_PAIR_ZC_MIN 8
 #endif
+#ifndef IGR_PAIR_ZC_MAX
+#define IGR_PAIR_ZC_MAX 128
+#endif
 // Launch shape of a two-sweep pass with NR rows per block.
 struct PairShape {
     int tiles_x, tiles_y, zc;
@@ -275,7 +278,7 @@ PairShape pair_shape(const Geom& g, int nr) {
     const long long tiles = (long long)sh.tiles_x * sh.tiles_y;
     long long zc = (tiles * g.n[2] + IGR_PAIR_BLOCKS - 1) / IGR_PAIR_BLOCKS;
     if (zc < IGR_PAIR_ZC_MIN) zc = IGR_PAIR_ZC_MIN;
-    if (zc > 128) zc = 128;
+    if (zc > IGR_PAIR_ZC_MAX) zc = IGR_PAIR_ZC_MAX;
     if (zc > g.n[2]) zc = g.n[2];
     sh.zc = int(zc);
     sh.blocks = tiles * ((g.n[2] + zc - 1) / zc);
