@@ -81,7 +81,7 @@ struct igr_ctx {
     void* d_Ub = nullptr;
     void* d_sig2 = nullptr;
     void* d_b = nullptr;
-    void* d_ir = nullptr;         // 1/rho written by the first sweep (FP64, split form)
+    void* d_ir = nullptr;         // 1/rho written by the first sweep (split form)
     void* d_Unb = nullptr;        // split form: the other FP32 state of the U^n / U^(n+1) ping-pong
     double* d_jet0 = nullptr;     // split form: zero jet states (ghosts of the stage differences)
     void* d_G = nullptr;          // viscous: the 9 velocity-gradient components (arithmetic type)
@@ -1261,7 +1261,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc(&c->d_Ub, 5 * field_bytes(c, c->dsize));
     if (!rc) rc = alloc(&c->d_sig2, field_bytes(c, c->ssize));
     if (!rc) rc = alloc(&c->d_b, field_bytes(c, c->csize));
-    if (!rc && (c->precision == IGR_F64 || split)) rc = alloc(&c->d_ir, field_bytes(c, c->csize));
+    if (!rc && split) rc = alloc(&c->d_ir, field_bytes(c, c->csize));
     if (!rc && split) rc = alloc(&c->d_Unb, 5 * field_bytes(c, c->esize));
     if (!rc && c->viscous) rc = alloc(&c->d_G, 9 * field_bytes(c, c->csize));
     if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));

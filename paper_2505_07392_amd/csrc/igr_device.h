@@ -106,8 +106,10 @@ struct Plain {
     using TS = T;   // Sigma
     using RU = typename S::R;
     static constexpr bool SPLIT = false;
-    // the first sweep of a solve stores 1/rho for the later sweeps (FP64)
-    static constexpr bool IRS = sizeof(C) == 8;
+    // later sweeps read rho and divide (in FP64 a stored 1/rho, the same
+    // bytes as rho, measured slower: its store costs the first pass more
+    // than the divisions cost the memory-bound later passes)
+    static constexpr bool IRS = false;
     template <bool HASD>
     __device__ __forceinline__ static RU load_u(const TB* b, const TD*, long long o) {
         return S::load_raw(b + o);

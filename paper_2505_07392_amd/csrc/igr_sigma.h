@@ -337,9 +337,9 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
     using RU = typename F::RU;
     using SS = Storage<typename F::TS>;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
-    // the first sweep stores 1/rho (interior and the face-ghost layer) and
-    // later sweeps read it instead of dividing again (FP64: the same bytes
-    // as rho; split form: one FP32 value instead of a base and a difference)
+    // the split form's first sweep stores 1/rho (interior and the face-ghost
+    // layer) and later sweeps read it (one FP32 value instead of a base and
+    // a difference)
     constexpr bool IRS = F::IRS;
     // 1-D grid in XCD-aware order: consecutive logical tiles (x fastest,
     // then y, then z chunk) run on one XCD, so rows shared by y-neighbour
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
 
 
 // Two Jacobi sweeps per pass over memory, for the sweeps after the first
-// one of a solve (the source b and, in FP64, 1/rho were stored by the
+// one of a solve (the source b and, in the split form, 1/rho were stored by the
 // first sweep).  A block of 64 x NR threads owns the columns x0..x0+63 of
 // rows y0-1..y0+NR-2 and marches through a chunk of z planes; its output
 // is the 64 x (NR-2) tile of rows y0..y0+NR-3 (level 2 needs level 1 on a
@@ -641,7 +641,7 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
 // FIRST: the first pass of a solve, which also forms the source b (eq. 9's
 // left side, second-order central velocity gradients) at every level-1
 // cell from u = m/rho in LDS (x/y neighbours) and a register queue (z), and
-// stores b and, in FP64, 1/rho for the later passes -- the work of the
+// stores b and, in the split form, 1/rho for the later passes -- the work of the
 // single first sweep fused into the pair.  With SPD (FIRST) it also loads
 // E and forms the CFL speed (cfl_speed, the standalone reduction's
 // expression) of every interior cell of its output tile and chunk; each
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
     static_assert(!SPD || FIRST, "the CFL maxima need the first pass's state loads");
     using C = typename F::C;
     using SS = Storage<typename F::TS>;
-    constexpr bool IRS = F::IRS;           // 1/rho stored by the first pass (FP64, split form)
+    constexpr bool IRS = F::IRS;           // 1/rho stored by the first pass (split form)
     constexpr int PD = 2;                   // planes loaded ahead (= register slots)
     constexpr int W0 = 68;                  // input row: columns x0-2 .. x0+65
     constexpr int W1 = 66;                  // level-1 and b row: x0-1 .. x0+64
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                     for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
                 bn = alpha * (tr2 + tr * tr);
                 if (outp && z >= z0 && z < z1) {
-                    // b and (FP64) 1/rho, face-ghost layer included, for the later passes
+                    // b and (split form) 1/rho, face-ghost layer included, for the later passes
                     const long long o = (long long)(z + G) * sz + (long long)(gy + G) * sy + (gx + G);
                     b[o] = bn;
                     if constexpr (IRS) {
