@@ -255,18 +255,21 @@ def _final_fields(s, U, S, gamma):
     return fin
 
 
-def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None):
+def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None, mu: float = 0.0,
+               zeta: float = 0.0):
     """Multi-jet box in each precision form (FP64 first): the rate over
     `steps` CFL steps after `warmup` (igr_advance, HIP-event timing of every
     launch), the device memory in use, and the per-field rel L1 error of the
     six fields and the derived pressure against the FP64 run after
     `err_steps` steps from the initial state with one fixed dt (0.8 x the
-    FP64 CFL step of the initial state)."""
+    FP64 CFL step of the initial state).  mu, zeta: shear and bulk viscosity
+    of eq. (5) (the viscous terms run in FP64 and FP32 only)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
 
     w = jet_workload(n, err_steps)
+    w.mu, w.zeta = mu, zeta
     say = log or (lambda m: print(m, file=sys.stderr, flush=True))
     out, ref, dt = {}, None, None
     for prec in forms:
@@ -335,6 +338,9 @@ def main():
                     help="Sigma pass structure: 1 single sweeps, 2 two-sweep passes (0: library default)")
     ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "rbgs"], help="Sigma sweeps")
+    ap.add_argument("--mu", type=float, default=0.0,
+                    help="shear viscosity of eq. (5) (viscous terms; FP64 and FP32 forms only)")
+    ap.add_argument("--zeta", type=float, default=0.0, help="bulk viscosity of eq. (5)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -363,10 +369,16 @@ def main():
                           "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
     forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
+    viscous = args.mu > 0.0 or args.zeta > 0.0
+    if viscous:
+        if args.precision not in ("f64", "f32"):
+            sys.exit("bench.py: the viscous terms run in the f64 and f32 forms only")
+        forms_req = [f for f in forms_req if f in ("f64", "f32")]
 
     if args.workload == "multi_jet":
         n = args.n or 1024
-        w, res, dt_err = jets_forms(n, [args.precision] + forms_req, args.steps, args.warmup, args.err_steps)
+        w, res, dt_err = jets_forms(n, [args.precision] + forms_req, args.steps, args.warmup, args.err_steps,
+                                    mu=args.mu, zeta=args.zeta)
         main_form = res.pop(args.precision)
         cells, el, kt, sb = w.cells, main_form["elapsed_s"], main_form.pop("kernel_times"), main_form["sigma_block"]
         workload = f"multi_jet_{n}"
@@ -374,16 +386,23 @@ def main():
                 f"face (rho 0.5, p 8, +-5 % seeded u_x), ambient (1, 0, 1), outflow elsewhere, "
                 f"{w.nsweeps} Jacobi sweeps, alpha = 4 dx^2 (not dx^2: the Mach-3 jet edges lose positivity "
                 f"at alpha = dx^2), CFL 0.5")
+        if viscous:
+            workload += "_viscous"
+            desc += f", viscous terms of eq. (5) with mu = {args.mu:g}, zeta = {args.zeta:g}"
     else:
         n = args.n or 256
         print(f"[bench] generating the {n}^3 periodic box", file=sys.stderr, flush=True)
         w = inputs.periodic_box(n=n, seed=0)
+        w.mu, w.zeta = args.mu, args.zeta
         cells = w.cells
         el, kt, sb = run_form(w, args.precision, args.steps, args.warmup, args.sigma_block, args.order,
                               args.smoother)
         workload = f"periodic_box_{n}"
         desc = (f"{workload}: periodic box {n}^3, rms Mach 1.5, alpha = dx^2, {w.nsweeps} Jacobi sweeps, "
                 f"CFL 0.5")
+        if viscous:
+            workload += "_viscous"
+            desc += f", viscous terms of eq. (5) with mu = {args.mu:g}, zeta = {args.zeta:g}"
         main_form = None
 
     value = cells * args.steps / el

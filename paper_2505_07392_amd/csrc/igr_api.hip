@@ -43,10 +43,11 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 enum KernelId {
-    K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT, K_SUMS, K_RESID, K_SWEEP, K_ADJOINT, K_VISCOUS, K_COUNT
+    K_BC_STATE, K_BC_SIGMA, K_SOURCE, K_JACOBI, K_FLUX, K_DT,
+    K_SUMS,     K_RESID,    K_SWEEP,  K_ADJOINT, K_VISCOUS, K_STRESS, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"bc_state", "bc_sigma", "source",  "jacobi", "flux_rk", "dt",
-                                           "sums",     "resid",    "sweep",   "adjoint", "viscous"};
+                                           "sums",     "resid",    "sweep",   "adjoint", "viscous", "stress"};
 
 struct TimingRecord {
     int kernel;
@@ -84,7 +85,7 @@ struct igr_ctx {
     void* d_ir = nullptr;         // 1/rho written by the first sweep (split form)
     void* d_Unb = nullptr;        // split form: the other FP32 state of the U^n / U^(n+1) ping-pong
     double* d_jet0 = nullptr;     // split form: zero jet states (ghosts of the stage differences)
-    void* d_G = nullptr;          // viscous: the 9 velocity-gradient components (arithmetic type)
+    void* d_G = nullptr;          // viscous: the 6 stress components (arithmetic type)
     double* d_partial = nullptr;
     double* d_scalars = nullptr;  // [0] dt, [1..5] sums, [6] residual
     double* d_speed = nullptr;    // per-flux-block CFL maxima left by a step's last stage
@@ -578,28 +579,59 @@ long long flux_blocks(const igr_ctx* c) {
 }
 
 // Viscous terms added to `out` (the right-hand side, or the stage the
-// flux kernel just wrote) from the stage input U (+ D): velocity gradients,
-// their ghosts, then the viscous flux divergence.  IGR_F64 and IGR_F32.
-template <class F, int MODE, bool HASD = false>
-int viscous_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, FluxOut<F, MODE>* out,
-                 const double* dtp, double dt_fixed, hipStream_t s) {
+// flux kernel just wrote) from the stage input U: the stress, its ghosts,
+// then the tiled viscous flux divergence.  IGR_F64 and IGR_F32.  Tile
+// heights (blocks of TY + 1 waves): FP64 7 (225 VGPRs at 2 waves per SIMD,
+// no spill; 1024^3: 51.6 ms per launch, against 72 ms with the face
+// stencils loaded whole and 108 ms without face sharing), FP32 11 (3 waves
+// per SIMD; 24.6 ms, TY = 8 28.6 ms).  The stress kernel marches z in
+// chunks of IGR_STRESS_ZC planes.
+#ifndef IGR_VISC_TY_F64
+#define IGR_VISC_TY_F64 7
+#endif
+#ifndef IGR_VISC_TY_F32
+#define IGR_VISC_TY_F32 11
+#endif
+#ifndef IGR_VISC_MINW_F64
+#define IGR_VISC_MINW_F64 2
+#endif
+#ifndef IGR_VISC_MINW_F32
+#define IGR_VISC_MINW_F32 3
+#endif
+#ifndef IGR_STRESS_ZC
+#define IGR_STRESS_ZC 32
+#endif
+#ifndef IGR_VISC_BLOCKS
+#define IGR_VISC_BLOCKS 2048
+#endif
+template <class F, int MODE>
+int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, const double* dtp, double dt_fixed,
+                 hipStream_t s) {
     if constexpr (F::SPLIT || sizeof(typename F::TB) < 4) {
         return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
     } else {
         using C = typename F::C;
-        C* Gm = static_cast<C*>(c->d_G);
+        constexpr int TY = sizeof(C) == 8 ? IGR_VISC_TY_F64 : IGR_VISC_TY_F32;
+        constexpr int MW = sizeof(C) == 8 ? IGR_VISC_MINW_F64 : IGR_VISC_MINW_F32;
+        C* T6 = static_cast<C*>(c->d_G);
         const Geom& g = c->g;
-        IGR_TRY(launch(c, K_VISCOUS, s, [&] {
-            k_vel_grad<F, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, g);
+        const FluxLaunch L = flux_launch(g, TY, IGR_VISC_BLOCKS);
+        if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the viscous launch");
+        const int szc = std::min(IGR_STRESS_ZC, g.n[2]);
+        const dim3 sgrid(unsigned((g.n[0] + STRESS_TX - 1) / STRESS_TX), unsigned((g.n[1] + STRESS_TY - 1) / STRESS_TY),
+                         unsigned((g.n[2] + szc - 1) / szc));
+        IGR_TRY(launch(c, K_STRESS, s, [&] {
+            k_stress<F><<<sgrid, dim3(STRESS_TX, STRESS_TY), 0, s>>>(U, T6, g, c->mu, c->zeta, szc);
         }));
-        for (int q = 0; q < 9; ++q) IGR_TRY(fill_sigma_ghosts(c, Gm + (size_t)q * g.fs, s));
+        for (int q = 0; q < 6; ++q) IGR_TRY(fill_sigma_ghosts(c, T6 + (size_t)q * g.fs, s));
         return launch(c, K_VISCOUS, s, [&] {
+            const dim3 grid(unsigned(L.blocks())), block(VISC_TX, TY + 1);
             if (c->order == 3)
-                k_viscous<F, MODE, 3, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, out, dtp, dt_fixed, g,
-                                                                                 c->mu, c->zeta);
+                k_viscous_tiled<F, MODE, TY, 3, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
+                                                                      L.tiles_y, L.zc);
             else
-                k_viscous<F, MODE, 5, HASD><<<cell_grid(g), cell_block(), 0, s>>>(U, D, Gm, out, dtp, dt_fixed, g,
-                                                                                 c->mu, c->zeta);
+                k_viscous_tiled<F, MODE, TY, 5, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
+                                                                      L.tiles_y, L.zc);
         });
     }
 }
@@ -630,7 +662,7 @@ int rhs_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, typename F::TB*
     IGR_TRY(fill_state_ghosts(c, U, s));
     IGR_TRY(sigma_solve_impl<F>(c, U, sig, c->nsweeps, s));
     IGR_TRY((flux_impl<F, MODE_RHS>(c, U, nullptr, sig, nullptr, rhs, nullptr, 0.0, s)));
-    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_RHS>(c, U, nullptr, rhs, nullptr, 0.0, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_RHS>(c, U, rhs, nullptr, 0.0, s)));
     return IGR_OK;
 }
 
@@ -685,7 +717,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(solve(NoD{}, U, nullptr));
     }
     IGR_TRY((flux_impl<F, MODE_STAGE1>(c, U, nullptr, cur, nullptr, Ua, dtp, dt_fixed, s)));
-    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, nullptr, Ua, dtp, dt_fixed, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, Ua, dtp, dt_fixed, s)));
     if constexpr (F::SPLIT) {
         // stage 2: U2 - Un = 1/4 ((U1 - Un) + dt L(U1)), U1 = Un + Ua
         IGR_TRY(fill_state_ghosts(c, Ua, s, true));
@@ -701,7 +733,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(fill_state_ghosts(c, Ua, s));
         IGR_TRY(solve(NoD{}, Ua, nullptr));
         IGR_TRY((flux_impl<F, MODE_STAGE2>(c, Ua, nullptr, cur, U, Ub, dtp, dt_fixed, s)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, nullptr, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, Ub, dtp, dt_fixed, s)));
         // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
         // solve ended in the scratch copy the kernel also writes Sigma's interior
         // into the caller's buffer (its ghosts are scratch)
@@ -709,7 +741,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(solve(NoD{}, Ub, nullptr));
         IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s, speed,
                                            cur != sig ? sig : nullptr)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, Unew, dtp, dt_fixed, s)));
     }
     return IGR_OK;
 }
@@ -1263,7 +1295,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc(&c->d_b, field_bytes(c, c->csize));
     if (!rc && split) rc = alloc(&c->d_ir, field_bytes(c, c->csize));
     if (!rc && split) rc = alloc(&c->d_Unb, 5 * field_bytes(c, c->esize));
-    if (!rc && c->viscous) rc = alloc(&c->d_G, 9 * field_bytes(c, c->csize));
+    if (!rc && c->viscous) rc = alloc(&c->d_G, 6 * field_bytes(c, c->csize));
     if (!rc) rc = alloc((void**)&c->d_partial, 5 * RED_BLOCKS * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
@@ -1294,7 +1326,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
             hipMemset(c->d_Ub, 0, 5 * field_bytes(c, c->dsize)) != hipSuccess ||
             hipMemset(c->d_sig2, 0, field_bytes(c, c->ssize)) != hipSuccess ||
             (split && hipMemset(c->d_Unb, 0, 5 * field_bytes(c, c->esize)) != hipSuccess) ||
-            (c->viscous && hipMemset(c->d_G, 0, 9 * field_bytes(c, c->csize)) != hipSuccess) ||
+            (c->viscous && hipMemset(c->d_G, 0, 6 * field_bytes(c, c->csize)) != hipSuccess) ||
             hipMemset(c->d_b, 0, field_bytes(c, c->csize)) != hipSuccess ||
             hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             rc = fail(IGR_EHIP, "scratch initialisation failed");

@@ -334,7 +334,6 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
                                                  double* __restrict__ speed, int* __restrict__ flag) {
     static_assert(!SPD || FIRST, "the CFL maxima need the first sweep's state loads");
     using C = typename F::C;
-    using RU = typename F::RU;
     using SS = Storage<typename F::TS>;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
     // the split form's first sweep stores 1/rho (interior and the face-ghost

@@ -4,43 +4,114 @@
 // that the inviscid flux kernel has already written ("sequential summation
 // of right-hand side contributions"):
 //
-//   k_vel_grad   G at interior cells by second-order central differences of
-//                u = m / rho (the paper: second-order derivatives of u
-//                suffice); ghost cells of G follow Sigma's rule (k_bc_sigma
-//                per component);
-//   k_viscous    per cell and direction d, the viscous flux at both faces:
-//                each side's tau e_d reconstructed from the cell-centre
-//                stresses with the weights of the conserved variables
-//                (Algorithm 1 reconstructs the gradients with the same
-//                coefficients; tau is linear in G), each side's velocity
-//                from the reconstructed conserved variables, and the mean
-//                of the two sides' fluxes -tau e_d (momenta) and
-//                -(u . tau) e_d (energy); the divergence is scaled by the
-//                stage's weight of dt and added to the output.
+//   k_stress          tau at interior cells from G by second-order central
+//                     differences of u = m / rho (the paper: second-order
+//                     derivatives of u suffice).  tau is symmetric: six
+//                     stored components (xx, xy, xz, yy, yz, zz).  Their
+//                     ghost cells follow Sigma's rule (k_bc_sigma per
+//                     component; that rule copies values, so it commutes
+//                     with the linear map G -> tau);
+//   k_viscous_tiled   per cell and direction d, the viscous flux at both
+//                     faces: each side's tau e_d reconstructed from the
+//                     cell-centre stresses with the weights of the conserved
+//                     variables (Algorithm 1 reconstructs the gradients with
+//                     the same coefficients; tau is linear in G), each
+//                     side's velocity from the reconstructed conserved
+//                     variables, and the mean of the two sides' fluxes
+//                     -tau e_d (momenta) and -(u . tau) e_d (energy); the
+//                     divergence is scaled by the stage's weight of dt and
+//                     added to the output.
+//
+// k_viscous_tiled follows the flux kernel's layout: a block owns a 64 x TY
+// tile of the x-y plane and marches through a chunk of z planes.  The
+// column's seven z-stencil fields (rho, m, tau_xz, tau_yz, tau_zz) of
+// planes k-2..k+3 sit in a register queue; plane k's nine in-plane fields
+// (rho, m, tau_xx, tau_xy, tau_xz, tau_yy, tau_yz) with a three-cell halo
+// are staged in LDS for the x and y stencils.  Every face is computed
+// once: x faces i+1/2 and y faces j+1/2 by the tile's own waves, the tile's
+// left x faces and lower y faces by one extra wave, the z face k+1/2 from
+// the queue (face k-1/2 is kept from the previous plane); x/y face fluxes
+// go through LDS.  Every input value is read from HBM about once (the halo
+// from L2), against seven times per direction for a kernel that reads each
+// stencil from global memory.
 #pragma once
 
 #include "igr_flux.h"
 
 namespace igr {
 
-template <class F, bool HASD>
-__global__ __launch_bounds__(256) void k_vel_grad(const typename F::TB* __restrict__ U,
-                                                  const typename F::TD* __restrict__ D,
-                                                  typename F::C* __restrict__ Gout, Geom g) {
+// index of tau_ab (a <= b) among the six stored components
+__host__ __device__ constexpr int tau_index(int a, int b) {
+    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : tau_index(b, a);
+}
+
+// One thread per (i, j) column marching through a chunk of zc planes: rho
+// and m of planes k-1, k, k+1 stay in registers (plane k+2 is fetched one
+// iteration ahead), the x and y neighbours come through the caches, so
+// that each input plane is read from HBM about once.  Block 64 x 4.
+constexpr int STRESS_TX = 64, STRESS_TY = 4;
+template <class F>
+__global__ __launch_bounds__(STRESS_TX* STRESS_TY) void k_stress(const typename F::TB* __restrict__ U,
+                                                                 typename F::C* __restrict__ T6, Geom g,
+                                                                 double mu_, double zeta_, int zc) {
     using C = typename F::C;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    using SU = Storage<typename F::TB>;
+    const int i = blockIdx.x * STRESS_TX + threadIdx.x;
+    const int j = blockIdx.y * STRESS_TY + threadIdx.y;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    const long long o = cell_offset(g, i, j, k);
+    const int z0 = blockIdx.z * zc;
+    const int z1 = min(z0 + zc, g.n[2]);
     const long long fs = g.fs;
-    auto get = [&](long long off) { return F::cvt(F::template load_u<HASD>(U, D, off)); };
-    for (int d = 0; d < 3; ++d) {
-        const long long op = o + g.st[d], om = o - g.st[d];
-        const C irp = C(1) / get(op), irm = C(1) / get(om);
-        const C sc = C(0.5) * C(g.ih[d]);
-        for (int c = 0; c < 3; ++c)
-            Gout[(3 * c + d) * fs + o] = (get((1 + c) * fs + op) * irp - get((1 + c) * fs + om) * irm) * sc;
+    const long long sz = g.st[2];
+    const long long o0 = cell_offset(g, i, j, z0);
+    auto get = [&](long long off) { return C(SU::load(U + off)); };
+    // rho, m_x, m_y, m_z of planes k-1 (qm), k (q0), k+1 (qp), k+2 (nxt)
+    C qm[4], q0[4], qp[4], nxt[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        qm[f] = get(f * fs + o0 - 2 * sz);
+        q0[f] = get(f * fs + o0 - sz);
+        qp[f] = get(f * fs + o0);
+        nxt[f] = get(f * fs + o0 + sz);
+    }
+    const C mu = C(mu_), lam = C(zeta_) - C(2) * C(mu_) / C(3);
+    for (int k = z0; k < z1; ++k) {
+        const long long o = o0 + (long long)(k - z0) * sz;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            qm[f] = q0[f];
+            q0[f] = qp[f];
+            qp[f] = nxt[f];
+        }
+        // plane k+2 exists (ghost layers reach nz+2) while k+1 < z1
+        if (k + 1 < z1) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) nxt[f] = get(f * fs + o + 2 * sz);
+        }
+        C Gm[3][3];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const long long op = o + g.st[d], om = o - g.st[d];
+            const C irp = C(1) / get(op), irm = C(1) / get(om);
+            const C sc = C(0.5) * C(g.ih[d]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Gm[c][d] = (get((1 + c) * fs + op) * irp - get((1 + c) * fs + om) * irm) * sc;
+        }
+        {
+            const C irp = C(1) / qp[0], irm = C(1) / qm[0];
+            const C sc = C(0.5) * C(g.ih[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Gm[c][2] = (qp[1 + c] * irp - qm[1 + c] * irm) * sc;
+        }
+        const C div = Gm[0][0] + Gm[1][1] + Gm[2][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                C t = mu * (Gm[a][b] + Gm[b][a]);
+                if (a == b) t += lam * div;
+                T6[tau_index(a, b) * fs + o] = t;
+            }
     }
 }
 
@@ -51,85 +122,296 @@ __device__ __forceinline__ double viscous_weight() {
     return MODE == MODE_STAGE2 ? 0.25 : (MODE == MODE_STAGE3 ? 2.0 / 3.0 : 1.0);
 }
 
-template <class F, int MODE, int ORDER, bool HASD>
-__global__ __launch_bounds__(256) void k_viscous(const typename F::TB* __restrict__ U,
-                                                 const typename F::TD* __restrict__ D,
-                                                 const typename F::C* __restrict__ Gp, FluxOut<F, MODE>* out,
-                                                 const double* __restrict__ dtp, double dt_fixed, Geom g,
-                                                 double mu_, double zeta_) {
-    using C = typename F::C;
-    using SO = Storage<FluxOut<F, MODE>>;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long long o = cell_offset(g, i, j, k);
-    const long long fs = g.fs;
-    const C mu = C(mu_), lam = C(zeta_) - C(2) * C(mu_) / C(3);
-    auto get = [&](long long off) { return F::cvt(F::template load_u<HASD>(U, D, off)); };
-    auto gr = [&](int a, int b, long long off) { return Gp[(3 * a + b) * fs + off]; };   // d u_a / d x_b
-    C Lv[4] = {C(0), C(0), C(0), C(0)};   // momenta, energy
-    for (int d = 0; d < 3; ++d) {
-        // cells i-3 .. i+3 along d: conserved (rho, m) and the stress column tau_kd
-        C v[7][4], t[7][3];
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            const long long oq = o + (long long)(q - 3) * g.st[d];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) v[q][f] = get(f * fs + oq);
-            const C div = gr(0, 0, oq) + gr(1, 1, oq) + gr(2, 2, oq);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                C tk = mu * (gr(c, d, oq) + gr(d, c, oq));
-                if (c == d) tk += lam * div;
-                t[q][c] = tk;
-            }
-        }
-        // faces i-1/2 (s = 0: cells q = 0..5) and i+1/2 (s = 1: q = 1..6)
-        C Fm[2][3], Fe[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            C rL[4], rR[4], tL[3], tR[3];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                if constexpr (ORDER == 5) {
-                    rL[f] = recon_left(v[s][f], v[s + 1][f], v[s + 2][f], v[s + 3][f], v[s + 4][f]);
-                    rR[f] = recon_right(v[s + 1][f], v[s + 2][f], v[s + 3][f], v[s + 4][f], v[s + 5][f]);
-                } else {
-                    rL[f] = recon3_left(v[s + 1][f], v[s + 2][f], v[s + 3][f]);
-                    rR[f] = recon3_right(v[s + 2][f], v[s + 3][f], v[s + 4][f]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if constexpr (ORDER == 5) {
-                    tL[c] = recon_left(t[s][c], t[s + 1][c], t[s + 2][c], t[s + 3][c], t[s + 4][c]);
-                    tR[c] = recon_right(t[s + 1][c], t[s + 2][c], t[s + 3][c], t[s + 4][c], t[s + 5][c]);
-                } else {
-                    tL[c] = recon3_left(t[s + 1][c], t[s + 2][c], t[s + 3][c]);
-                    tR[c] = recon3_right(t[s + 2][c], t[s + 3][c], t[s + 4][c]);
-                }
-            }
-            const C iL = C(1) / rL[0], iR = C(1) / rR[0];
-            C eL = C(0), eR = C(0);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Fm[s][c] = C(-0.5) * (tL[c] + tR[c]);
-                eL += rL[1 + c] * iL * tL[c];
-                eR += rR[1 + c] * iR * tR[c];
-            }
-            Fe[s] = C(-0.5) * (eL + eR);
-        }
-        const C ih = C(g.ih[d]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Lv[c] -= (Fm[1][c] - Fm[0][c]) * ih;
-        Lv[3] -= (Fe[1] - Fe[0]) * ih;
+// the two sides of the face between cells 2 and 3 of v[0..5]
+template <class C, int ORDER>
+__device__ __forceinline__ void recon_face(C v0, C v1, C v2, C v3, C v4, C v5, C& l, C& r) {
+    if constexpr (ORDER == 5) {
+        l = recon_left(v0, v1, v2, v3, v4);
+        r = recon_right(v1, v2, v3, v4, v5);
+    } else {
+        l = recon3_left(v1, v2, v3);
+        r = recon3_right(v2, v3, v4);
     }
-    const C w = MODE == MODE_RHS ? C(1) : C(viscous_weight<MODE>() * (dtp ? *dtp : dt_fixed));
+}
+
+// Viscous flux of the face between cells 2 and 3 of v[f][0..5] (fields
+// rho, m_x, m_y, m_z, then tau_xd, tau_yd, tau_zd of the face's direction
+// d): per side the momenta's flux is -tau e_d and the energy's
+// -(u . tau) e_d with u = m / rho of that side; Fv is the mean of the two
+// sides (Fv[0..2] momenta, Fv[3] energy).  The fields go one at a time
+// (rho, then each m_c with tau_cd), so that only running sums stay live.
+template <class C, int ORDER, class Win>
+__device__ __forceinline__ void viscous_face(Win win, C (&Fv)[4]) {
+    C v[6];
+    win(0, v);
+    C rl, rr;
+    recon_face<C, ORDER>(v[0], v[1], v[2], v[3], v[4], v[5], rl, rr);
+    const C il = C(1) / rl, ir = C(1) / rr;
+    C el = C(0), er = C(0);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const long long of = (1 + f) * fs + o;
-        SO::store(out + of, SO::load(out + of) + w * Lv[f]);
+    for (int c = 0; c < 3; ++c) {
+        C ml, mr, tl, tr;
+        win(1 + c, v);
+        recon_face<C, ORDER>(v[0], v[1], v[2], v[3], v[4], v[5], ml, mr);
+        win(4 + c, v);
+        recon_face<C, ORDER>(v[0], v[1], v[2], v[3], v[4], v[5], tl, tr);
+        Fv[c] = C(-0.5) * (tl + tr);
+        el += ml * il * tl;
+        er += mr * ir * tr;
+    }
+    Fv[3] = C(-0.5) * (el + er);
+}
+
+constexpr int VISC_TX = 64;
+// in-plane fields staged in LDS: rho, m_x, m_y, m_z, tau_xx, tau_xy,
+// tau_xz, tau_yy, tau_yz; the x stencil reads fields 0-3 and 4, 5, 6
+// (tau_xx, tau_yx, tau_zx), the y stencil 0-3 and 5, 7, 8 (tau_xy,
+// tau_yy, tau_zy)
+constexpr int VISC_NF = 9;
+
+// F: Plain<double> or Plain<float>.  U: the stage input (ghosts filled);
+// T6: its stress (ghosts filled); out: the stage output that the flux
+// kernel wrote (or the right-hand side), read and written pointwise.
+// Block: 64 x (TY + 1) threads; wave w < TY owns row w of the tile, wave
+// TY computes the extra row of y faces and the x faces at the tile's left
+// edge.  All faces of one direction run through one instruction sequence.
+template <class F, int MODE, int TY, int ORDER, int MINW>
+__global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const typename F::TB* __restrict__ U,
+                                                                           const typename F::C* __restrict__ T6,
+                                                                           FluxOut<F, MODE>* out,
+                                                                           const double* __restrict__ dtp,
+                                                                           double dt_fixed, Geom g, int tiles_x,
+                                                                           int tiles_y, int zc) {
+    using C = typename F::C;
+    using SU = Storage<typename F::TB>;
+    using SO = Storage<FluxOut<F, MODE>>;
+    static_assert(std::is_same_v<typename F::TB, C>, "the plain forms store the arithmetic type");
+    constexpr int TX = VISC_TX;
+    constexpr int W = TX + 2 * G;
+    constexpr int H = TY + 2 * G;
+    constexpr int NF = VISC_NF;
+    __shared__ C pl[NF][H][W];
+    __shared__ C fx[4][TY][TX + 1];
+    __shared__ C fy[4][TY + 1][TX];
+
+    const int lane = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int tid = wv * TX + lane;
+    int tx, ty, cz;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, tx, ty, cz);
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = cz * zc;
+    const int z1 = min(z0 + zc, nz);
+    const long long fs = g.fs;
+    const int sy = g.st[1], sz = g.st[2];
+    const C ihx = C(g.ih[0]), ihy = C(g.ih[1]), ihz = C(g.ih[2]);
+    const C wdt = MODE == MODE_RHS ? C(1) : C(viscous_weight<MODE>() * (dtp ? *dtp : dt_fixed));
+
+    // this thread's column (waves < TY)
+    const int i = x0 + lane;
+    const int j = y0 + wv;
+    const bool own = wv < TY;
+    const bool col_load = own && i < nx + G && j < ny + G;
+    const bool col_out = own && i < nx && j < ny;
+    const uint32_t col = uint32_t((j + G) * sy + (i + G));
+
+    // Field f (0..8 the in-plane fields, 9 tau_zz) at in-plane offset o of
+    // a plane: a uniform plane base plus a 32-bit offset per lane
+    auto plane_of = [&](auto* a, int f, int plane) {
+        plane = __builtin_amdgcn_readfirstlane(plane);
+        return a + ((long long)f * fs + (long long)(plane + G) * sz);
+    };
+    auto ldf = [&](int f, int plane, uint32_t o) -> C {
+        const C* a = f < 4 ? U + (long long)f * fs : T6 + (long long)(f - 4) * fs;
+        return SU::load(at_plane(plane_of(a, 0, plane), o));
+    };
+    // the column's z-stencil fields: rho, m, tau_xz, tau_yz, tau_zz
+    auto zfield = [](int f) { return f < 4 ? f : (f == 4 ? 6 : (f == 5 ? 8 : 9)); };
+    auto load_col = [&](int plane, C (&v)[7]) {
+#pragma unroll
+        for (int f = 0; f < 7; ++f) v[f] = ldf(zfield(f), plane, col);
+    };
+
+    // register queue: slot p holds plane k-2+p of the seven z fields;
+    // columns that are never loaded keep a valid state (their faces are
+    // evaluated but discarded)
+    C q[7][6];
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+#pragma unroll
+        for (int p = 0; p < 6; ++p) q[f][p] = f == 0 ? C(1) : C(0);
+    C nxt[7];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) nxt[f] = f == 0 ? C(1) : C(0);
+    if (col_load) {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            C v[7];
+            load_col(z0 - 3 + p, v);
+#pragma unroll
+            for (int f = 0; f < 7; ++f) q[f][p + 1] = v[f];
+        }
+        load_col(z0 + 2, nxt);
+    }
+    // the column's in-plane stresses that the queue lacks (tau_xx, tau_xy,
+    // tau_yy), one plane ahead
+    constexpr int PF[3] = {4, 5, 7};
+    C pw[3] = {C(0), C(0), C(0)};
+    if (col_load) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) pw[e] = ldf(PF[e], z0, col);
+    }
+
+    // halo of the next plane, prefetched into registers: the y-halo (2G
+    // rows x TX columns x NF fields) row by row to the waves (lane =
+    // column, coalesced), the x-halo (2G columns x TY rows x NF fields) to
+    // the first NF * 2G * TY threads
+    constexpr int NW = TY + 1;
+    constexpr int NYR = NF * 2 * G;
+    constexpr int HY = (NYR + NW - 1) / NW;
+    constexpr int NXH = NF * 2 * G * TY;
+    static_assert(NXH <= TX * NW, "x halo needs one thread per cell");
+    C hy[HY], hx = C(0);
+    auto y_slot = [&](int s, int& f, int& cy) -> bool {
+        const int rf = wv + s * NW;
+        if (rf >= NYR) return false;
+        f = rf / (2 * G);
+        const int rr = rf - f * 2 * G;
+        cy = rr < G ? rr - G : TY + (rr - G);
+        const int gy = y0 + cy;
+        return i < nx + G && gy >= -G && gy < ny + G;
+    };
+    auto x_slot = [&](int& f, int& cx, int& cy) -> bool {
+        if (tid >= NXH) return false;
+        f = tid / (2 * G * TY);
+        const int r = tid - f * 2 * G * TY;
+        cy = r / (2 * G);
+        const int c = r - cy * 2 * G;
+        cx = c < G ? c - G : TX + (c - G);
+        const int gx = x0 + cx;
+        return gx >= -G && gx < nx + G && (y0 + cy) < ny + G;
+    };
+    auto load_halo = [&](int plane) {
+#pragma unroll
+        for (int s = 0; s < HY; ++s) {
+            int f, cy;
+            hy[s] = C(0);
+            if (y_slot(s, f, cy)) hy[s] = ldf(f, plane, uint32_t((y0 + cy + G) * sy + (i + G)));
+        }
+        int f, cx, cy;
+        hx = C(0);
+        if (x_slot(f, cx, cy)) hx = ldf(f, plane, uint32_t((y0 + cy + G) * sy + (x0 + cx + G)));
+    };
+    load_halo(z0);
+
+    C Fz_prev[4] = {C(0), C(0), C(0), C(0)};
+    for (int k = z0 - 1; k < z1; ++k) {
+        // shift the queue; slots hold k-2..k+3 afterwards
+#pragma unroll
+        for (int f = 0; f < 7; ++f) {
+#pragma unroll
+            for (int p = 0; p < 5; ++p) q[f][p] = q[f][p + 1];
+            q[f][5] = nxt[f];
+        }
+        if (col_load && k + 1 < z1) load_col(k + 4, nxt);
+        C ov[4] = {C(0), C(0), C(0), C(0)};
+        if (k >= z0) {
+            // the output's old values, read while the plane is staged
+            if (col_out) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) ov[f] = C(SO::load(at_plane(plane_of(out, 1 + f, k), col)));
+            }
+            // A: stage plane k (the tile from the queue and the prefetched
+            // in-plane stresses, the halo from the prefetched registers),
+            // then prefetch the halo and in-plane stresses of plane k+1
+            if (own) {
+                pl[0][wv + G][lane + G] = q[0][2];
+                pl[1][wv + G][lane + G] = q[1][2];
+                pl[2][wv + G][lane + G] = q[2][2];
+                pl[3][wv + G][lane + G] = q[3][2];
+                pl[4][wv + G][lane + G] = pw[0];
+                pl[5][wv + G][lane + G] = pw[1];
+                pl[6][wv + G][lane + G] = q[4][2];
+                pl[7][wv + G][lane + G] = pw[2];
+                pl[8][wv + G][lane + G] = q[5][2];
+            }
+#pragma unroll
+            for (int s = 0; s < HY; ++s) {
+                int f, cy;
+                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = hy[s];
+            }
+            {
+                int f, cx, cy;
+                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = hx;
+            }
+            if (k + 1 < z1) {
+                load_halo(k + 1);
+                if (col_load) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) pw[e] = ldf(PF[e], k + 1, col);
+                }
+            }
+            __syncthreads();
+            // B1: x faces.  Waves < TY: face (x0+lane)+1/2 of row wv; wave
+            // TY, lanes < TY: face x0-1/2 of row `lane`.  The face's stencil
+            // (cells left-2 .. left+3) sits in LDS columns fi .. fi+5.
+            {
+                constexpr int XF[7] = {0, 1, 2, 3, 4, 5, 6};
+                const int r = own ? wv : lane;
+                const int fi = own ? lane + 1 : 0;
+                if (own || lane < TY) {
+                    C Fv[4];
+                    viscous_face<C, ORDER>(
+                        [&](int f, C (&v)[6]) {
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) v[c] = pl[XF[f]][r + G][fi + c];
+                        },
+                        Fv);
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) fx[f][r][fi] = Fv[f];
+                }
+            }
+            // B2: y faces.  Waves < TY: face (y0+wv)+1/2 of column lane;
+            // wave TY: face y0-1/2.  Stencil rows fj .. fj+5.
+            {
+                constexpr int YF[7] = {0, 1, 2, 3, 5, 7, 8};
+                const int fj = own ? wv + 1 : 0;
+                C Fv[4];
+                viscous_face<C, ORDER>(
+                    [&](int f, C (&v)[6]) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) v[c] = pl[YF[f]][fj + c][lane + G];
+                    },
+                    Fv);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) fy[f][fj][lane] = Fv[f];
+            }
+            __syncthreads();
+        }
+        // z face k+1/2 from the queue (after the x and y faces: fewer
+        // values live across them)
+        C Fz[4];
+        viscous_face<C, ORDER>(
+            [&](int f, C (&v)[6]) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) v[c] = q[f][c];
+            },
+            Fz);
+        // C: flux differences (x, y, z) and the stage update
+        if (k >= z0 && col_out) {
+            C Lv[4] = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+            for (int f = 0; f < 4; ++f) Lv[f] -= (fx[f][wv][lane + 1] - fx[f][wv][lane]) * ihx;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) Lv[f] -= (fy[f][wv + 1][lane] - fy[f][wv][lane]) * ihy;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) Lv[f] -= (Fz[f] - Fz_prev[f]) * ihz;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) SO::store(at_plane(plane_of(out, 1 + f, k), col), ov[f] + wdt * Lv[f]);
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) Fz_prev[f] = Fz[f];
     }
 }
 
