@@ -584,8 +584,9 @@ long long flux_blocks(const igr_ctx* c) {
 // heights (blocks of TY + 1 waves): FP64 7 (225 VGPRs at 2 waves per SIMD,
 // no spill; 1024^3: 51.6 ms per launch, against 72 ms with the face
 // stencils loaded whole and 108 ms without face sharing), FP32 11 (3 waves
-// per SIMD; 24.6 ms, TY = 8 28.6 ms).  The stress kernel marches z in
-// chunks of IGR_STRESS_ZC planes.
+// per SIMD; 24.6 ms, TY = 8 28.6 ms).  The stress kernel: 64 x 16 tiles
+// (1024^3 FP64 16.2 ms, FP32 12.5 ms; TY = 8 19.8 / 13.9 ms; a column
+// march without LDS 26.3 / 15.8 ms).
 #ifndef IGR_VISC_TY_F64
 #define IGR_VISC_TY_F64 7
 #endif
@@ -598,8 +599,11 @@ long long flux_blocks(const igr_ctx* c) {
 #ifndef IGR_VISC_MINW_F32
 #define IGR_VISC_MINW_F32 3
 #endif
-#ifndef IGR_STRESS_ZC
-#define IGR_STRESS_ZC 32
+#ifndef IGR_STRESS_TY
+#define IGR_STRESS_TY 16
+#endif
+#ifndef IGR_STRESS_BLOCKS
+#define IGR_STRESS_BLOCKS 4096
 #endif
 #ifndef IGR_VISC_BLOCKS
 #define IGR_VISC_BLOCKS 2048
@@ -617,11 +621,11 @@ int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, con
         const Geom& g = c->g;
         const FluxLaunch L = flux_launch(g, TY, IGR_VISC_BLOCKS);
         if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the viscous launch");
-        const int szc = std::min(IGR_STRESS_ZC, g.n[2]);
-        const dim3 sgrid(unsigned((g.n[0] + STRESS_TX - 1) / STRESS_TX), unsigned((g.n[1] + STRESS_TY - 1) / STRESS_TY),
-                         unsigned((g.n[2] + szc - 1) / szc));
+        const FluxLaunch LS = flux_launch(g, IGR_STRESS_TY, IGR_STRESS_BLOCKS);
+        if (LS.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the stress launch");
         IGR_TRY(launch(c, K_STRESS, s, [&] {
-            k_stress<F><<<sgrid, dim3(STRESS_TX, STRESS_TY), 0, s>>>(U, T6, g, c->mu, c->zeta, szc);
+            k_stress<F, IGR_STRESS_TY><<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
+                U, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
         }));
         for (int q = 0; q < 6; ++q) IGR_TRY(fill_sigma_ghosts(c, T6 + (size_t)q * g.fs, s));
         return launch(c, K_VISCOUS, s, [&] {

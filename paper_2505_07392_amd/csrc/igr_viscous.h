@@ -45,38 +45,92 @@ __host__ __device__ constexpr int tau_index(int a, int b) {
     return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : tau_index(b, a);
 }
 
-// One thread per (i, j) column marching through a chunk of zc planes: rho
-// and m of planes k-1, k, k+1 stay in registers (plane k+2 is fetched one
-// iteration ahead), the x and y neighbours come through the caches, so
-// that each input plane is read from HBM about once.  Block 64 x 4.
-constexpr int STRESS_TX = 64, STRESS_TY = 4;
-template <class F>
-__global__ __launch_bounds__(STRESS_TX* STRESS_TY) void k_stress(const typename F::TB* __restrict__ U,
-                                                                 typename F::C* __restrict__ T6, Geom g,
-                                                                 double mu_, double zeta_, int zc) {
+// A block owns a 64 x TY tile of the x-y plane and marches a chunk of z
+// planes: rho and m of planes k-1, k, k+1 of its columns stay in a register
+// queue (plane k+2 is fetched one iteration ahead), plane k with a one-cell
+// halo is staged in LDS for the x and y differences (the halo of plane k+1
+// is fetched while plane k is processed), so that each input value is read
+// from HBM about once.
+constexpr int STRESS_TX = 64;
+template <class F, int TY>
+__global__ __launch_bounds__(STRESS_TX* TY) void k_stress(const typename F::TB* __restrict__ U,
+                                                          typename F::C* __restrict__ T6, Geom g, double mu_,
+                                                          double zeta_, int tiles_x, int tiles_y, int zc) {
     using C = typename F::C;
     using SU = Storage<typename F::TB>;
-    const int i = blockIdx.x * STRESS_TX + threadIdx.x;
-    const int j = blockIdx.y * STRESS_TY + threadIdx.y;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const int z0 = blockIdx.z * zc;
-    const int z1 = min(z0 + zc, g.n[2]);
+    constexpr int TX = STRESS_TX;
+    __shared__ C pl[4][TY + 2][TX + 2];
+    const int lane = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int tid = wv * TX + lane;
+    int tx, ty, cz;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, tx, ty, cz);
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = cz * zc;
+    const int z1 = min(z0 + zc, nz);
     const long long fs = g.fs;
-    const long long sz = g.st[2];
-    const long long o0 = cell_offset(g, i, j, z0);
-    auto get = [&](long long off) { return C(SU::load(U + off)); };
+    const int sy = g.st[1], sz = g.st[2];
+    const int i = x0 + lane, j = y0 + wv;
+    // cells up to n (the last interior cell's + neighbour) are loaded
+    const bool col_load = i < nx + 1 && j < ny + 1;
+    const bool col_out = i < nx && j < ny;
+    const uint32_t col = uint32_t((j + G) * sy + (i + G));
+    auto ld = [&](int f, int plane, uint32_t o) -> C {
+        plane = __builtin_amdgcn_readfirstlane(plane);
+        return C(SU::load(at_plane(U + ((long long)f * fs + (long long)(plane + G) * sz), o)));
+    };
     // rho, m_x, m_y, m_z of planes k-1 (qm), k (q0), k+1 (qp), k+2 (nxt)
+    // after the shift at the top of iteration k
     C qm[4], q0[4], qp[4], nxt[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        qm[f] = get(f * fs + o0 - 2 * sz);
-        q0[f] = get(f * fs + o0 - sz);
-        qp[f] = get(f * fs + o0);
-        nxt[f] = get(f * fs + o0 + sz);
+    for (int f = 0; f < 4; ++f) qm[f] = q0[f] = qp[f] = nxt[f] = f == 0 ? C(1) : C(0);
+    if (col_load) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            q0[f] = ld(f, z0 - 1, col);
+            qp[f] = ld(f, z0, col);
+            nxt[f] = ld(f, z0 + 1, col);
+        }
     }
+    // one-cell halo: the y rows (2 rows x TX columns x 4 fields) row by row
+    // to the waves, the x columns (2 x TY x 4) to the first 8 TY threads
+    constexpr int NYR = 4 * 2;
+    constexpr int HY = (NYR + TY - 1) / TY;
+    constexpr int NXH = 4 * 2 * TY;
+    C hy[HY], hx = C(0);
+    auto y_slot = [&](int s, int& f, int& cy) -> bool {
+        const int rf = wv + s * TY;
+        if (rf >= NYR) return false;
+        f = rf >> 1;
+        cy = (rf & 1) ? TY : -1;
+        const int gy = y0 + cy;
+        return i < nx + 1 && gy >= -1 && gy < ny + 1;
+    };
+    auto x_slot = [&](int& f, int& cx, int& cy) -> bool {
+        if (tid >= NXH) return false;
+        f = tid / (2 * TY);
+        const int r = tid - f * 2 * TY;
+        cy = r >> 1;
+        cx = (r & 1) ? TX : -1;
+        const int gx = x0 + cx;
+        return gx >= -1 && gx < nx + 1 && y0 + cy < ny + 1;
+    };
+    auto load_halo = [&](int plane) {
+#pragma unroll
+        for (int s = 0; s < HY; ++s) {
+            int f, cy;
+            hy[s] = C(0);
+            if (y_slot(s, f, cy)) hy[s] = ld(f, plane, uint32_t((y0 + cy + G) * sy + (i + G)));
+        }
+        int f, cx, cy;
+        hx = C(0);
+        if (x_slot(f, cx, cy)) hx = ld(f, plane, uint32_t((y0 + cy + G) * sy + (x0 + cx + G)));
+    };
+    load_halo(z0);
     const C mu = C(mu_), lam = C(zeta_) - C(2) * C(mu_) / C(3);
+    const C scx = C(0.5) * C(g.ih[0]), scy = C(0.5) * C(g.ih[1]), scz = C(0.5) * C(g.ih[2]);
     for (int k = z0; k < z1; ++k) {
-        const long long o = o0 + (long long)(k - z0) * sz;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             qm[f] = q0[f];
@@ -84,34 +138,54 @@ __global__ __launch_bounds__(STRESS_TX* STRESS_TY) void k_stress(const typename 
             qp[f] = nxt[f];
         }
         // plane k+2 exists (ghost layers reach nz+2) while k+1 < z1
-        if (k + 1 < z1) {
+        if (col_load && k + 1 < z1) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f) nxt[f] = get(f * fs + o + 2 * sz);
+            for (int f = 0; f < 4; ++f) nxt[f] = ld(f, k + 2, col);
         }
-        C Gm[3][3];
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-            const long long op = o + g.st[d], om = o - g.st[d];
-            const C irp = C(1) / get(op), irm = C(1) / get(om);
-            const C sc = C(0.5) * C(g.ih[d]);
+        for (int f = 0; f < 4; ++f) pl[f][wv + 1][lane + 1] = q0[f];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Gm[c][d] = (get((1 + c) * fs + op) * irp - get((1 + c) * fs + om) * irm) * sc;
+        for (int s = 0; s < HY; ++s) {
+            int f, cy;
+            if (y_slot(s, f, cy)) pl[f][cy + 1][lane + 1] = hy[s];
         }
         {
-            const C irp = C(1) / qp[0], irm = C(1) / qm[0];
-            const C sc = C(0.5) * C(g.ih[2]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Gm[c][2] = (qp[1 + c] * irp - qm[1 + c] * irm) * sc;
+            int f, cx, cy;
+            if (x_slot(f, cx, cy)) pl[f][cy + 1][cx + 1] = hx;
         }
-        const C div = Gm[0][0] + Gm[1][1] + Gm[2][2];
+        if (k + 1 < z1) load_halo(k + 1);
+        __syncthreads();
+        if (col_out) {
+            C Gm[3][3];
+            {
+                const C irp = C(1) / pl[0][wv + 1][lane + 2], irm = C(1) / pl[0][wv + 1][lane];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = a; b < 3; ++b) {
-                C t = mu * (Gm[a][b] + Gm[b][a]);
-                if (a == b) t += lam * div;
-                T6[tau_index(a, b) * fs + o] = t;
+                for (int c = 0; c < 3; ++c)
+                    Gm[c][0] = (pl[1 + c][wv + 1][lane + 2] * irp - pl[1 + c][wv + 1][lane] * irm) * scx;
             }
+            {
+                const C irp = C(1) / pl[0][wv + 2][lane + 1], irm = C(1) / pl[0][wv][lane + 1];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    Gm[c][1] = (pl[1 + c][wv + 2][lane + 1] * irp - pl[1 + c][wv][lane + 1] * irm) * scy;
+            }
+            {
+                const C irp = C(1) / qp[0], irm = C(1) / qm[0];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Gm[c][2] = (qp[1 + c] * irp - qm[1 + c] * irm) * scz;
+            }
+            const C div = Gm[0][0] + Gm[1][1] + Gm[2][2];
+            C* tp = T6 + (long long)(k + G) * sz;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = a; b < 3; ++b) {
+                    C t = mu * (Gm[a][b] + Gm[b][a]);
+                    if (a == b) t += lam * div;
+                    *at_plane(tp + (long long)tau_index(a, b) * fs, col) = t;
+                }
+        }
+        __syncthreads();
     }
 }
 
