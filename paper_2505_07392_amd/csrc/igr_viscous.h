@@ -59,6 +59,7 @@ __global__ __launch_bounds__(STRESS_TX* TY) void k_stress(const typename F::TB* 
     using C = typename F::C;
     using SU = Storage<typename F::TB>;
     constexpr int TX = STRESS_TX;
+    static_assert(TX * TY <= 1024, "at most 1024 threads per block");
     __shared__ C pl[4][TY + 2][TX + 2];
     const int lane = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -158,19 +159,19 @@ __global__ __launch_bounds__(STRESS_TX* TY) void k_stress(const typename F::TB* 
         if (col_out) {
             C Gm[3][3];
             {
-                const C irp = C(1) / pl[0][wv + 1][lane + 2], irm = C(1) / pl[0][wv + 1][lane];
+                const C irp = fast_rcp(pl[0][wv + 1][lane + 2]), irm = fast_rcp(pl[0][wv + 1][lane]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     Gm[c][0] = (pl[1 + c][wv + 1][lane + 2] * irp - pl[1 + c][wv + 1][lane] * irm) * scx;
             }
             {
-                const C irp = C(1) / pl[0][wv + 2][lane + 1], irm = C(1) / pl[0][wv][lane + 1];
+                const C irp = fast_rcp(pl[0][wv + 2][lane + 1]), irm = fast_rcp(pl[0][wv][lane + 1]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     Gm[c][1] = (pl[1 + c][wv + 2][lane + 1] * irp - pl[1 + c][wv][lane + 1] * irm) * scy;
             }
             {
-                const C irp = C(1) / qp[0], irm = C(1) / qm[0];
+                const C irp = fast_rcp(qp[0]), irm = fast_rcp(qm[0]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Gm[c][2] = (qp[1 + c] * irp - qm[1 + c] * irm) * scz;
             }
@@ -220,7 +221,7 @@ __device__ __forceinline__ void viscous_face(Win win, C (&Fv)[4]) {
     win(0, v);
     C rl, rr;
     recon_face<C, ORDER>(v[0], v[1], v[2], v[3], v[4], v[5], rl, rr);
-    const C il = C(1) / rl, ir = C(1) / rr;
+    const C il = fast_rcp(rl), ir = fast_rcp(rr);
     C el = C(0), er = C(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
     using SU = Storage<typename F::TB>;
     using SO = Storage<FluxOut<F, MODE>>;
     static_assert(std::is_same_v<typename F::TB, C>, "the plain forms store the arithmetic type");
+    static_assert(VISC_TX * (TY + 1) <= 1024, "at most 1024 threads per block");
     constexpr int TX = VISC_TX;
     constexpr int W = TX + 2 * G;
     constexpr int H = TY + 2 * G;
