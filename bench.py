@@ -95,6 +95,12 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":
         return 4 * eu + c          # rho, m read; b written
+    if kernel == "stress":
+        return 4 * eu + 6 * c      # rho, m read; the six stress components written
+    if kernel == "viscous":
+        # rho, m and the six stress components read; the stage's four momentum
+        # and energy fields read and written
+        return 4 * eu + 6 * c + 8 * eu
     if kernel == "dt":
         return 5 * eu
     raise KeyError(kernel)
@@ -102,10 +108,13 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
 
 def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
     """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
-    Sigma kernels from their measured average launch time (sigma_block: the
+    Sigma kernels (and, when they ran, the viscous stress and flux
+    divergence) from their measured average launch time (sigma_block: the
     pass structure the context ran)."""
     out = {}
-    for k in ("flux_rk", "jacobi"):
+    for k in ("flux_rk", "jacobi", "stress", "viscous"):
+        if k not in kt:
+            continue
         ms, cnt = kt[k]
         if cnt:
             ab = algorithmic_bytes_per_cell(k, precision, nsweeps, sigma_block, smoother) * cells

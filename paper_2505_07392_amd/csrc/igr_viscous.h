@@ -339,21 +339,24 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
         for (int e = 0; e < 3; ++e) pw[e] = ldf(PF[e], z0, col);
     }
 
-    // halo of the next plane, prefetched into registers: the y-halo (2G
-    // rows x TX columns x NF fields) row by row to the waves (lane =
-    // column, coalesced), the x-halo (2G columns x TY rows x NF fields) to
-    // the first NF * 2G * TY threads
+    // halo of the next plane, prefetched into registers.  The y stencils
+    // read rho, m, tau_xy, tau_yy, tau_yz and the x stencils rho, m,
+    // tau_xx, tau_xy, tau_xz (seven of the nine fields each), so only
+    // those are fetched: the y-halo (2G rows x TX columns x 7 fields) row
+    // by row to the waves (lane = column, coalesced), the x-halo (2G
+    // columns x TY rows x 7 fields) to the first 7 * 2G * TY threads
     constexpr int NW = TY + 1;
-    constexpr int NYR = NF * 2 * G;
+    constexpr int NYR = 7 * 2 * G;
     constexpr int HY = (NYR + NW - 1) / NW;
-    constexpr int NXH = NF * 2 * G * TY;
+    constexpr int NXH = 7 * 2 * G * TY;
     static_assert(NXH <= TX * NW, "x halo needs one thread per cell");
     C hy[HY], hx = C(0);
     auto y_slot = [&](int s, int& f, int& cy) -> bool {
         const int rf = wv + s * NW;
         if (rf >= NYR) return false;
-        f = rf / (2 * G);
-        const int rr = rf - f * 2 * G;
+        const int q = rf / (2 * G);
+        f = q < 4 ? q : (q == 4 ? 5 : (q == 5 ? 7 : 8));
+        const int rr = rf - q * 2 * G;
         cy = rr < G ? rr - G : TY + (rr - G);
         const int gy = y0 + cy;
         return i < nx + G && gy >= -G && gy < ny + G;

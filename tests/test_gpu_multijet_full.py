@@ -2,8 +2,13 @@
 configuration the multi-jet rates are measured with (FP64, 10 sweeps,
 alpha = 4 dx^2, two-sweep Sigma passes with a two-sweep first pass, flux z
 chunks of 64 planes at 512^3 and 128 planes at 1024^3 -- the benchmark's
-own workload): one igr_step of the whole box on the GPU, and the oracle's
-step on windows around sampled cells.
+own workload), and at 1024^3 also with the viscous terms (eqs. (2)-(3),
+(5); the benchmark's viscous configuration's launches, here with
+mu = 1e-4 and zeta = 5e-5 so that both stress terms carry weight): one
+igr_step of the whole box on the GPU, and the oracle's step on windows
+around sampled cells.  The viscous terms reach 4 cells per stage (a
+gradient, then a 3-cell reconstruction), inside the 3 + S + 1 of the flux
+on Sigma, so the window below holds for them too.
 
 One SSP-RK3 step of a cell depends on the state within 3 (3 + S + 1) = 42
 cells (three stages, each a flux stencil of 3 cells on Sigma solved with S
@@ -43,10 +48,15 @@ SAMPLES = {512: [(64, 74, 1), (320, 190, 14), (192, 448, 8), (508, 3, 500)],
            1024: [(128, 138, 1), (640, 382, 14), (384, 896, 8), (1020, 3, 1020)]}
 
 
-def _workload(n):
+# (box size, shear viscosity, bulk viscosity) of each case
+CASES = {"512": (512, 0.0, 0.0), "1024": (1024, 0.0, 0.0), "1024_viscous": (1024, 1e-4, 5e-5)}
+
+
+def _workload(n, mu=0.0, zeta=0.0):
     w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10,
                          build_state=False)
     w.alpha = 4.0 * w.dx * w.dx
+    w.mu, w.zeta = mu, zeta
     return w
 
 
@@ -74,12 +84,12 @@ def _axis_window(c, n):
     return np.arange(c - R, c + R + 1), True
 
 
-@pytest.fixture(scope="module", params=sorted(SAMPLES))
+@pytest.fixture(scope="module", params=sorted(CASES))
 def gpu_step(request):
-    N = request.param
-    w = _workload(N)
+    N, mu, zeta = CASES[request.param]
+    w = _workload(N, mu, zeta)
     dt = _dt(w)
-    banner(f"multi-jet {N}^3 FP64: filling the state")
+    banner(f"multi-jet {N}^3 FP64 (mu {mu:g}, zeta {zeta:g}): filling the state")
     s = igr.Solver.from_workload(w, precision="f64")
     assert s.sigma_block == 2
     U = s.new_state()
@@ -96,7 +106,7 @@ def gpu_step(request):
     for k, j, i in SAMPLES[N]:
         idx, sl = blk(k, j, i)
         assert np.array_equal(U[(slice(None),) + sl].cpu().numpy(), inputs.multi_jet_state_at(w, *idx))
-    banner(f"multi-jet {N}^3 FP64: one igr_step, dt = {dt:.6e}")
+    banner(f"multi-jet {N}^3 FP64 (mu {mu:g}): one igr_step, dt = {dt:.6e}")
     s.step(U, S, dt_fixed=dt)
     out = {}
     for k, j, i in SAMPLES[N]:
@@ -127,7 +137,7 @@ def _oracle_window(w, dt, sample):
         patches = tuple(ref.Patch(jt.yc - js[0] * w.dy, jt.zc - ks[0] * w.dz, jt.r, jt.rho, jt.ux, jt.uy, jt.uz,
                                   jt.p, jt.width) for jt in w.jets)
     prob = ref.Problem(len(is_), len(js), len(ks), w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha,
-                       faces=tuple(faces), patches=patches, nsweeps=w.nsweeps)
+                       faces=tuple(faces), patches=patches, nsweeps=w.nsweeps, mu=w.mu, zeta=w.zeta)
     Uo, So = ref.rk3_step(prob, torch.from_numpy(U0), torch.zeros(prob.shape, dtype=torch.float64), dt)
     Uo, So = Uo.numpy(), So.numpy()
     # the compared block in window coordinates
@@ -145,7 +155,7 @@ def oracle_windows(gpu_step):
     N, w, dt, _ = gpu_step
     out = {}
     for sample in SAMPLES[N]:
-        banner(f"multi-jet {N}^3: oracle window around {sample}")
+        banner(f"multi-jet {N}^3 (mu {w.mu:g}): oracle window around {sample}")
         out[sample] = _oracle_window(w, dt, sample)
     scale = np.max([v[3] for v in out.values()], axis=0)
     return out, scale
