@@ -357,6 +357,9 @@ def main():
         print("bench.py measures one GPU only: this library has no multi-GPU path (the halo-exchange "
               "design is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    viscous = args.mu > 0.0 or args.zeta > 0.0
+    if viscous and args.precision not in ("f64", "f32"):
+        sys.exit("bench.py: the viscous terms run in the f64 and f32 forms only")
 
     import torch
 
@@ -378,10 +381,7 @@ def main():
                           "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
     forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
-    viscous = args.mu > 0.0 or args.zeta > 0.0
     if viscous:
-        if args.precision not in ("f64", "f32"):
-            sys.exit("bench.py: the viscous terms run in the f64 and f32 forms only")
         forms_req = [f for f in forms_req if f in ("f64", "f32")]
 
     if args.workload == "multi_jet":

@@ -122,3 +122,4 @@ def test_null_context_calls():
 def test_kernel_names():
     names = igr.kernel_names()
     assert "flux_rk" in names and "jacobi" in names
+    assert "stress" in names and "viscous" in names

@@ -1,0 +1,56 @@
+"""Host logic of bench.py (no GPU): argument checks that end the run before
+any device call, and the algorithmic byte model the roofline fractions
+divide by."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16", "bf16d"])
+def test_viscous_terms_need_f64_or_f32(prec):
+    r = _run("--mu", "1e-5", "--precision", prec)
+    assert r.returncode != 0
+    assert "f64 and f32 forms only" in r.stderr
+
+
+def test_byte_model():
+    """Values per cell: flux stage 1 reads U and Sigma and writes U (11),
+    stages 2 and 3 also read U^n (16); the stress reads rho and m and writes
+    six components; the viscous flux divergence reads rho, m and the six
+    components and reads and writes four output fields."""
+    assert bench.algorithmic_bytes_per_cell("flux_rk", "f64", 10) == 8 * (11 + 16 + 16) / 3
+    assert bench.algorithmic_bytes_per_cell("flux_rk", "f32", 10) == 4 * (11 + 16 + 16) / 3
+    assert bench.algorithmic_bytes_per_cell("stress", "f64", 10) == 8 * 10
+    assert bench.algorithmic_bytes_per_cell("stress", "f32", 10) == 4 * 10
+    assert bench.algorithmic_bytes_per_cell("viscous", "f64", 10) == 8 * 18
+    assert bench.algorithmic_bytes_per_cell("viscous", "f32", 10) == 4 * 18
+    with pytest.raises(KeyError):
+        bench.algorithmic_bytes_per_cell("nonesuch", "f64", 10)
+
+
+def test_rooflines_skip_kernels_that_did_not_run():
+    kt = {"flux_rk": (84.0, 2), "jacobi": (0.0, 0), "stress": (0.0, 0), "viscous": (0.0, 0)}
+    r = bench.kernel_rooflines(kt, 1000, "f64", 10, 2)
+    assert set(r) == {"flux_rk"}
+    gbs = bench.algorithmic_bytes_per_cell("flux_rk", "f64", 10) * 1000 / (42.0e-3) / 1e9
+    assert r["flux_rk"]["achieved_GBs"] == round(gbs, 1)
+    assert r["flux_rk"]["frac"] == round(gbs / bench.HBM_PEAK_GBS, 4)
