@@ -11,14 +11,14 @@
 //                     ghost cells follow Sigma's rule (k_bc_sigma per
 //                     component; that rule copies values, so it commutes
 //                     with the linear map G -> tau);
-//   k_viscous_tiled   per cell and direction d, the viscous flux at both
-//                     faces: each side's tau e_d reconstructed from the
-//                     cell-centre stresses with the weights of the conserved
-//                     variables (Algorithm 1 reconstructs the gradients with
-//                     the same coefficients; tau is linear in G), each
-//                     side's velocity from the reconstructed conserved
-//                     variables, and the mean of the two sides' fluxes
-//                     -tau e_d (momenta) and -(u . tau) e_d (energy); the
+//   k_viscous_tiled   per face of direction d, the viscous flux: each
+//                     side's tau e_d reconstructed from the cell-centre
+//                     stresses with the weights of the conserved variables
+//                     (Algorithm 1 reconstructs the gradients with the same
+//                     coefficients; tau is linear in G), each side's
+//                     velocity from the reconstructed conserved variables,
+//                     and the mean of the two sides' fluxes -tau e_d
+//                     (momenta) and -(u . tau) e_d (energy); each cell's
 //                     divergence is scaled by the stage's weight of dt and
 //                     added to the output.
 //
@@ -31,9 +31,10 @@
 // once: x faces i+1/2 and y faces j+1/2 by the tile's own waves, the tile's
 // left x faces and lower y faces by one extra wave, the z face k+1/2 from
 // the queue (face k-1/2 is kept from the previous plane); x/y face fluxes
-// go through LDS.  Every input value is read from HBM about once (the halo
-// from L2), against seven times per direction for a kernel that reads each
-// stencil from global memory.
+// go through LDS.  A tile's own columns are read from HBM once; its
+// in-plane halo is read again by the neighbouring tiles (about 1.4-1.5x
+// the compulsory bytes in all), where a kernel that reads every stencil
+// from global memory would fetch each z stencil seven times.
 #pragma once
 
 #include "igr_flux.h"

@@ -54,3 +54,16 @@ def test_rooflines_skip_kernels_that_did_not_run():
     gbs = bench.algorithmic_bytes_per_cell("flux_rk", "f64", 10) * 1000 / (42.0e-3) / 1e9
     assert r["flux_rk"]["achieved_GBs"] == round(gbs, 1)
     assert r["flux_rk"]["frac"] == round(gbs / bench.HBM_PEAK_GBS, 4)
+
+
+def test_source_hash_ignores_comments_only():
+    """The counter summaries are tied to the kernel code: comments and
+    layout do not change the hash, code does (string literals are code)."""
+    a = 'int f(int x) { return x + 1; }  // one\n/* two */ const char* s = "// not a comment";\n'
+    b = '// header\nint f(int x)\n{\n    return x + 1;   /* same */\n}\nconst char* s = "// not a comment";\n'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "// not a comment";\n'
+    d = 'int f(int x) { return x + 1; }\nconst char* s = "// a comment?";\n'
+    assert bench.strip_comments(a) == bench.strip_comments(b)
+    assert bench.strip_comments(a) != bench.strip_comments(c)
+    assert bench.strip_comments(a) != bench.strip_comments(d)
+    assert len(bench.kernel_source_hash()) == 16
