@@ -201,9 +201,9 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
 /* nsteps igr_step calls in one: the same states and time steps.  With a
  * CFL time step (dt_fixed <= 0) the maximum speed for step n+1 is formed
  * by step n's last stage as it writes the new state (the same FP64
- * expression as the standalone reduction, on the values as stored), so the
- * separate pass over U runs only before the first step (with viscous
- * terms every step forms its maximum as igr_step does).  If dt_last is not
+ * expression as the standalone reduction, on the values as stored; with
+ * viscous terms by their kernel, which completes the new state), so the
+ * separate pass over U runs only before the first step.  If dt_last is not
  * NULL the stream is synchronised, *dt_last
  * receives the last step's dt and the error flag is checked.
  * nsteps >= 0. */

@@ -608,14 +608,28 @@ long long flux_blocks(const igr_ctx* c) {
 #ifndef IGR_VISC_BLOCKS
 #define IGR_VISC_BLOCKS 2048
 #endif
+// tile height of the viscous flux divergence of arithmetic type C
+template <class C>
+constexpr int visc_ty() {
+    return sizeof(C) == 8 ? IGR_VISC_TY_F64 : IGR_VISC_TY_F32;
+}
+// blocks of one viscous flux-divergence launch of form F (the length of the
+// CFL maxima its last stage leaves)
+template <class F>
+long long visc_blocks(const igr_ctx* c) {
+    return flux_launch(c->g, visc_ty<typename F::C>(), IGR_VISC_BLOCKS).blocks();
+}
+
+// speed (last stage, nullable): the kernel also leaves the per-block CFL
+// maxima of the new state there (visc_blocks values).
 template <class F, int MODE>
 int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, const double* dtp, double dt_fixed,
-                 hipStream_t s) {
+                 hipStream_t s, double* speed = nullptr) {
     if constexpr (F::SPLIT || sizeof(typename F::TB) < 4) {
         return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
     } else {
         using C = typename F::C;
-        constexpr int TY = sizeof(C) == 8 ? IGR_VISC_TY_F64 : IGR_VISC_TY_F32;
+        constexpr int TY = visc_ty<C>();
         constexpr int MW = sizeof(C) == 8 ? IGR_VISC_MINW_F64 : IGR_VISC_MINW_F32;
         C* T6 = static_cast<C*>(c->d_G);
         const Geom& g = c->g;
@@ -632,10 +646,10 @@ int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, con
             const dim3 grid(unsigned(L.blocks())), block(VISC_TX, TY + 1);
             if (c->order == 3)
                 k_viscous_tiled<F, MODE, TY, 3, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
-                                                                      L.tiles_y, L.zc);
+                                                                      L.tiles_y, L.zc, speed, c->d_flag);
             else
                 k_viscous_tiled<F, MODE, TY, 5, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
-                                                                      L.tiles_y, L.zc);
+                                                                      L.tiles_y, L.zc, speed, c->d_flag);
         });
     }
 }
@@ -743,9 +757,11 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         // into the caller's buffer (its ghosts are scratch)
         IGR_TRY(fill_state_ghosts(c, Ub, s));
         IGR_TRY(solve(NoD{}, Ub, nullptr));
-        IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s, speed,
-                                           cur != sig ? sig : nullptr)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, Unew, dtp, dt_fixed, s)));
+        // with viscous terms their kernel, which completes the new state,
+        // forms the CFL maxima instead of the flux kernel
+        IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s,
+                                           c->viscous ? nullptr : speed, cur != sig ? sig : nullptr)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, Unew, dtp, dt_fixed, s, speed)));
     }
     return IGR_OK;
 }
@@ -779,27 +795,20 @@ int step_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, double cfl, do
 
 // nsteps steps.  With a CFL time step the first step's maximum comes from
 // the standalone reduction and every later one from the maxima that the
-// previous step's last stage left in d_speed (with viscous terms, which the
-// last stage adds after the flux kernel, every step forms its maxima the
-// way igr_step does).  The split form alternates between the caller's U and
-// its other FP32 state and copies the last state into U if it ends in the
-// other one.
+// previous step's last stage left in d_speed (the flux kernel's, or with
+// viscous terms the viscous kernel's, which completes the new state).  The
+// split form alternates between the caller's U and its other FP32 state
+// and copies the last state into U if it ends in the other one.
 template <class F>
 int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int nsteps, double cfl, double dt_fixed,
                  hipStream_t s) {
     using TB = typename F::TB;
     const bool use_cfl = !(dt_fixed > 0.0);
-    const bool fused = !c->viscous;
-    const int nblk = int(flux_blocks<F>(c));
+    const int nblk = int(c->viscous ? visc_blocks<F>(c) : flux_blocks<F>(c));
     TB* U = Ucaller;
     for (int n = 0; n < nsteps; ++n) {
         TB* Unew = next_state<F>(c, U, Ucaller);
         const double* dtp = nullptr;
-        if (use_cfl && !fused) {
-            IGR_TRY(step_stages<F>(c, U, Unew, sig, nullptr, dt_fixed, s, nullptr, true, cfl));
-            U = Unew;
-            continue;
-        }
         if (use_cfl) {
             if (n == 0) {
                 IGR_TRY(speed_dt_impl(c, (const TB*)U, cfl, s));
@@ -810,8 +819,7 @@ int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int n
             }
             dtp = c->d_scalars;
         }
-        IGR_TRY(step_stages<F>(c, U, Unew, sig, dtp, dt_fixed, s,
-                               fused && use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
+        IGR_TRY(step_stages<F>(c, U, Unew, sig, dtp, dt_fixed, s, use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
         U = Unew;
     }
     return settle_state<F>(c, U, Ucaller, s);
@@ -1304,13 +1312,19 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (!rc) rc = alloc((void**)&c->d_scalars, 8 * sizeof(double));
     if (!rc) rc = alloc((void**)&c->d_flag, sizeof(int));
     if (!rc) {
-        // per-block CFL maxima: of the last flux stage (FP32 arithmetic) or
-        // of the first sweep (FP64)
+        // per-block CFL maxima: of the last flux stage (igr_advance), of the
+        // first sweep or pass (FP64 igr_step), or of the last viscous
+        // launch (igr_advance with viscous terms)
         long long nb = c->precision == IGR_F64         ? flux_blocks<Plain<double>>(c)
                        : c->precision == IGR_F32_BF16D ? flux_blocks<Split>(c)
                                                        : flux_blocks<Plain<float>>(c);
         if (c->precision == IGR_F64 && sweep_speed_slots(c->g) > nb) nb = sweep_speed_slots(c->g);
         if (c->precision == IGR_F64 && pair_speed_slots(c->g) > nb) nb = pair_speed_slots(c->g);
+        // with viscous terms: of the last viscous flux-divergence launch
+        if (c->viscous) {
+            const long long nv = c->precision == IGR_F64 ? visc_blocks<Plain<double>>(c) : visc_blocks<Plain<float>>(c);
+            if (nv > nb) nb = nv;
+        }
         rc = alloc((void**)&c->d_speed, size_t(nb) * sizeof(double));
     }
     if (!rc && !c->patches.empty()) {

@@ -248,6 +248,9 @@ constexpr int VISC_NF = 9;
 // F: Plain<double> or Plain<float>.  U: the stage input (ghosts filled);
 // T6: its stress (ghosts filled); out: the stage output that the flux
 // kernel wrote (or the right-hand side), read and written pointwise.
+// speed (last stage, nullable): one CFL maximum per block of the new state
+// as stored (cfl_speed in FP64, as the standalone reduction forms it), for
+// the next step's dt; a non-physical new state sets *flag.
 // Block: 64 x (TY + 1) threads; wave w < TY owns row w of the tile, wave
 // TY computes the extra row of y faces and the x faces at the tile's left
 // edge.  All faces of one direction run through one instruction sequence.
@@ -257,7 +260,9 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
                                                                            FluxOut<F, MODE>* out,
                                                                            const double* __restrict__ dtp,
                                                                            double dt_fixed, Geom g, int tiles_x,
-                                                                           int tiles_y, int zc) {
+                                                                           int tiles_y, int zc,
+                                                                           double* __restrict__ speed,
+                                                                           int* __restrict__ flag) {
     using C = typename F::C;
     using SU = Storage<typename F::TB>;
     using SO = Storage<FluxOut<F, MODE>>;
@@ -385,6 +390,14 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
     };
     load_halo(z0);
 
+    // last stage: the CFL maximum of this thread's new cells, one LDS slot
+    // per thread (the register would stay live across the plane loop)
+    constexpr bool FUSE = MODE == MODE_STAGE3;
+    __shared__ double smax[FUSE ? VISC_TX * (TY + 1) : 1];
+    if (FUSE) smax[tid] = 0.0;
+    const bool spd = FUSE && speed != nullptr;
+    bool bad = false;
+
     C Fz_prev[4] = {C(0), C(0), C(0), C(0)};
     for (int k = z0 - 1; k < z1; ++k) {
         // shift the queue; slots hold k-2..k+3 afterwards
@@ -396,11 +409,15 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
         }
         if (col_load && k + 1 < z1) load_col(k + 4, nxt);
         C ov[4] = {C(0), C(0), C(0), C(0)};
+        C orho = C(1);
         if (k >= z0) {
-            // the output's old values, read while the plane is staged
+            // the output's old values, read while the plane is staged (and
+            // its density, which these terms leave as it is, for the CFL
+            // maximum of the last stage)
             if (col_out) {
 #pragma unroll
                 for (int f = 0; f < 4; ++f) ov[f] = C(SO::load(at_plane(plane_of(out, 1 + f, k), col)));
+                if (spd) orho = C(SO::load(at_plane(plane_of(out, 0, k), col)));
             }
             // A: stage plane k (the tile from the queue and the prefetched
             // in-plane stresses, the halo from the prefetched registers),
@@ -487,11 +504,32 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
             for (int f = 0; f < 4; ++f) Lv[f] -= (fy[f][wv + 1][lane] - fy[f][wv][lane]) * ihy;
 #pragma unroll
             for (int f = 0; f < 4; ++f) Lv[f] -= (Fz[f] - Fz_prev[f]) * ihz;
+            double vs[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) SO::store(at_plane(plane_of(out, 1 + f, k), col), ov[f] + wdt * Lv[f]);
+            for (int f = 0; f < 4; ++f) {
+                const C v = ov[f] + wdt * Lv[f];
+                SO::store(at_plane(plane_of(out, 1 + f, k), col), v);
+                vs[f] = double(SO::stored(v));
+            }
+            if (spd)
+                smax[tid] = fmax(smax[tid], cfl_speed(g, double(orho), vs[0], vs[1], vs[2], vs[3], bad));
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) Fz_prev[f] = Fz[f];
+    }
+    if (spd) {
+        // block maximum: each wave's slots by shuffles, then the waves
+        double m = smax[tid];
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        __syncthreads();
+        if (lane == 0) smax[wv] = m;
+        __syncthreads();
+        if (tid == 0) {
+            double mm = 0.0;
+            for (int w = 0; w <= TY; ++w) mm = fmax(mm, smax[w]);
+            speed[blockIdx.x] = mm;
+        }
+        if (bad) flag[0] = 1;
     }
 }
 

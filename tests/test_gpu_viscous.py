@@ -79,19 +79,27 @@ def test_viscous_steps(vcase):
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
 
 
-def test_viscous_advance_with_cfl_matches_steps():
-    """With viscosity igr_advance forms every time step with the standalone
-    reduction (the last stage's fused maxima would miss the viscous update):
-    the same states and time steps as igr_step calls."""
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_viscous_advance_with_cfl_matches_steps(prec):
+    """With viscosity igr_advance takes each later time step from the CFL
+    maxima that the last stage's viscous kernel forms as it completes the
+    new state; igr_step forms them from the state it starts from (FP64: in
+    its first Sigma pass, FP32: the standalone reduction).  Both evaluate the
+    same FP64 expression on the stored values (one rounding of dt allowed,
+    in case the compiler contracts it differently in the two kernels), so
+    the states agree to a few units of the arithmetic."""
     w = _viscous(CASES["mixed_70x9x7"]())
-    banner("viscous advance vs steps (FP32)")
-    s = igr.Solver.from_workload(w, precision="f32")
+    banner(f"viscous advance vs steps ({prec})")
+    s = igr.Solver.from_workload(w, precision=prec)
     U1, U2 = s.state_from(w.U), s.state_from(w.U)
     S1, S2 = s.field_from(_sigma0(w)), s.field_from(_sigma0(w))
     dts = [s.step(U1, S1, cfl=0.4) for _ in range(3)]
     dt_last = s.advance(U2, S2, 3, cfl=0.4)
-    assert dt_last == dts[-1]
-    assert np.array_equal(to_host(s, U1), to_host(s, U2))
+    assert abs(dt_last - dts[-1]) <= 1e-15 * dts[-1]
+    a, b = to_host(s, U1).astype(np.float64), to_host(s, U2).astype(np.float64)
+    d = rel_linf(b, a).max()
+    print(f"[gpu-case] viscous advance vs steps {prec}: max rel diff {d:.3e}", flush=True)
+    assert d <= (1e-14 if prec == "f64" else 1e-6)
 
 
 def test_viscous_conservation_periodic_box():
