@@ -301,7 +301,7 @@ def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None,
     six fields and the derived pressure against the FP64 run after
     `err_steps` steps from the initial state with one fixed dt (0.8 x the
     FP64 CFL step of the initial state).  mu, zeta: shear and bulk viscosity
-    of eq. (5) (the viscous terms run in FP64 and FP32 only)."""
+    of eq. (5) (the viscous terms run in the plain forms: not bf16d)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "rbgs"], help="Sigma sweeps")
     ap.add_argument("--mu", type=float, default=0.0,
-                    help="shear viscosity of eq. (5) (viscous terms; FP64 and FP32 forms only)")
+                    help="shear viscosity of eq. (5) (viscous terms; plain storage forms, not bf16d)")
     ap.add_argument("--zeta", type=float, default=0.0, help="bulk viscosity of eq. (5)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
@@ -387,8 +387,8 @@ def main():
               "design is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     viscous = args.mu > 0.0 or args.zeta > 0.0
-    if viscous and args.precision not in ("f64", "f32"):
-        sys.exit("bench.py: the viscous terms run in the f64 and f32 forms only")
+    if viscous and args.precision == "bf16d":
+        sys.exit("bench.py: the viscous terms run in the plain storage forms (f64, f32, f16, bf16), not bf16d")
 
     import torch
 
@@ -411,7 +411,7 @@ def main():
         return
     forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
     if viscous:
-        forms_req = [f for f in forms_req if f in ("f64", "f32")]
+        forms_req = [f for f in forms_req if f != "bf16d"]
 
     if args.workload == "multi_jet":
         n = args.n or 1024

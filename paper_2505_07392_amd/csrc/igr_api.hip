@@ -580,7 +580,7 @@ long long flux_blocks(const igr_ctx* c) {
 
 // Viscous terms added to `out` (the right-hand side, or the stage the
 // flux kernel just wrote) from the stage input U: the stress, its ghosts,
-// then the tiled viscous flux divergence.  IGR_F64 and IGR_F32.  Tile
+// then the tiled viscous flux divergence.  The plain forms.  Tile
 // heights (blocks of TY + 1 waves): FP64 7 (225 VGPRs at 2 waves per SIMD,
 // no spill; 1024^3: 50.3 ms per launch, against 72 ms with the face
 // stencils loaded whole and 108 ms without face sharing), FP32 11 (3 waves
@@ -625,8 +625,8 @@ long long visc_blocks(const igr_ctx* c) {
 template <class F, int MODE>
 int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, const double* dtp, double dt_fixed,
                  hipStream_t s, double* speed = nullptr) {
-    if constexpr (F::SPLIT || sizeof(typename F::TB) < 4) {
-        return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
+    if constexpr (F::SPLIT) {
+        return fail(IGR_EUNSUPPORTED, "viscous terms need a plain storage form (not IGR_F32_BF16D)");
     } else {
         using C = typename F::C;
         constexpr int TY = visc_ty<C>();
@@ -1223,8 +1223,8 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (opts->precision == IGR_F32_BF16D && opts->sigma_block > 2)
         return fail(IGR_EUNSUPPORTED, "IGR_F32_BF16D runs single or two-sweep Sigma passes (sigma_block 0..2)");
     if (!(opts->mu >= 0.0) || !(opts->zeta >= 0.0)) return fail(IGR_EINVAL, "viscosities must be >= 0");
-    if ((opts->mu > 0.0 || opts->zeta > 0.0) && opts->precision != IGR_F64 && opts->precision != IGR_F32)
-        return fail(IGR_EUNSUPPORTED, "viscous terms need IGR_F64 or IGR_F32");
+    if ((opts->mu > 0.0 || opts->zeta > 0.0) && opts->precision == IGR_F32_BF16D)
+        return fail(IGR_EUNSUPPORTED, "viscous terms need a plain storage form (not IGR_F32_BF16D)");
     if (opts->order != 5 && opts->order != 3)
         return fail(IGR_EUNSUPPORTED, "reconstruction order must be 5 or 3");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");
@@ -1322,6 +1322,7 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
         if (c->precision == IGR_F64 && pair_speed_slots(c->g) > nb) nb = pair_speed_slots(c->g);
         // with viscous terms: of the last viscous flux-divergence launch
         if (c->viscous) {
+            // (the 16-bit forms run the FP32-arithmetic shape)
             const long long nv = c->precision == IGR_F64 ? visc_blocks<Plain<double>>(c) : visc_blocks<Plain<float>>(c);
             if (nv > nb) nb = nv;
         }

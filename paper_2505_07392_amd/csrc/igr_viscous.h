@@ -245,7 +245,10 @@ constexpr int VISC_TX = 64;
 // tau_yy, tau_zy)
 constexpr int VISC_NF = 9;
 
-// F: Plain<double> or Plain<float>.  U: the stage input (ghosts filled);
+// F: a plain storage form (FP64, FP32, or 16-bit storage with FP32
+// arithmetic: the stage output that the flux kernel rounded to storage is
+// read back, the viscous increment added in FP32, and the sum rounded
+// again).  U: the stage input (ghosts filled);
 // T6: its stress (ghosts filled); out: the stage output that the flux
 // kernel wrote (or the right-hand side), read and written pointwise.
 // speed (last stage, nullable): one CFL maximum per block of the new state
@@ -266,7 +269,6 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
     using C = typename F::C;
     using SU = Storage<typename F::TB>;
     using SO = Storage<FluxOut<F, MODE>>;
-    static_assert(std::is_same_v<typename F::TB, C>, "the plain forms store the arithmetic type");
     static_assert(VISC_TX * (TY + 1) <= 1024, "at most 1024 threads per block");
     constexpr int TX = VISC_TX;
     constexpr int W = TX + 2 * G;
@@ -305,8 +307,15 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
         return a + ((long long)f * fs + (long long)(plane + G) * sz);
     };
     auto ldf = [&](int f, int plane, uint32_t o) -> C {
-        const C* a = f < 4 ? U + (long long)f * fs : T6 + (long long)(f - 4) * fs;
-        return SU::load(at_plane(plane_of(a, 0, plane), o));
+        if constexpr (std::is_same_v<typename F::TB, C>) {
+            // FP64 / FP32: one load through a selected base
+            const C* a = f < 4 ? U + (long long)f * fs : T6 + (long long)(f - 4) * fs;
+            return SU::load(at_plane(plane_of(a, 0, plane), o));
+        } else {
+            // 16-bit state, FP32 stress
+            if (f < 4) return C(SU::load(at_plane(plane_of(U, f, plane), o)));
+            return *at_plane(plane_of(T6, f - 4, plane), o);
+        }
     };
     // the column's z-stencil fields: rho, m, tau_xz, tau_yz, tau_zz
     auto zfield = [](int f) { return f < 4 ? f : (f == 4 ? 6 : (f == 5 ? 8 : 9)); };

@@ -85,7 +85,7 @@ def test_forms_against_f64_after_200_steps(reference, precision):
         assert all(v == v for v in err.values()), err
 
 
-# the viscous terms (eqs. (2)-(3), (5); FP64 and FP32 only): the FP32 form
+# the viscous terms (eqs. (2)-(3), (5)): the FP32 form
 # against the FP64 run (parity-tested against the oracle with the viscous
 # terms on 1024^3 windows) over 100 fixed-dt steps, at the FP32 bound
 VISC_MU, VISC_ZETA, VISC_STEPS = 1e-4, 5e-5, 100

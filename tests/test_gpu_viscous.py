@@ -3,8 +3,8 @@ eq. (5)) against the FP64 oracle, through the C ABI: right-hand sides and
 RK3 steps with shear and bulk viscosity on the mixed small cases (jet discs,
 periodic and outflow faces, ragged tiles), third-order reconstruction, the
 viscous contribution on its own (L(mu, zeta) - L(0, 0), at 1e-10 of its own
-size), conservation on a periodic box, the FP32 form, the 256^3 box on
-sampled windows, and the entry points that reject viscosity."""
+size), conservation on a periodic box, the FP32 and 16-bit storage forms, the
+256^3 box on sampled windows, and the entry points that reject viscosity."""
 
 import numpy as np
 import pytest
@@ -116,25 +116,34 @@ def test_viscous_conservation_periodic_box():
     assert (np.abs(t1 - t0) <= 1e-12 * scale).all(), (t1 - t0) / scale
 
 
-def test_viscous_fp32_form():
+# per-form bounds of the stored-precision forms (as without viscosity):
+# whole-state BF16 storage is held at its known-miss level only
+FORM_BOUND = {"f32": 1e-5, "f16": 3e-3, "bf16": 6e-2}
+
+
+@pytest.mark.parametrize("prec", sorted(FORM_BOUND))
+def test_viscous_precision_forms(prec):
+    """The FP32 form and the 16-bit storage forms (FP32 arithmetic; the
+    viscous kernel reads the stage output the flux kernel rounded to 16 bits
+    and rounds the sum again) against the FP64 oracle after 10 steps."""
     w = _viscous(inputs.periodic_box(n=32, seed=2))
-    banner("viscous FP32 form 32^3, 10 steps")
+    banner(f"viscous {prec} form 32^3, 10 steps")
     prob = problem_from(w)
     Uo = torch.from_numpy(w.U.copy())
     So = torch.zeros(prob.shape, dtype=torch.float64)
     dt = 0.8 * ref.compute_dt(prob, Uo, 0.5)
     for _ in range(10):
         Uo, So = ref.rk3_step(prob, Uo, So, dt)
-    s = igr.Solver.from_workload(w, precision="f32")
+    s = igr.Solver.from_workload(w, precision=prec)
     U = s.state_from(w.U)
     S = s.new_field()
     for _ in range(10):
         s.step(U, S, dt_fixed=dt, sync=False)
     s.check()
-    g, o = to_host(s, U), Uo.numpy()
+    g, o = to_host(s, U).astype(np.float64), Uo.numpy()
     err = np.abs(g - o).sum(axis=(1, 2, 3)) / np.abs(o).sum(axis=(1, 2, 3))
-    print(f"[gpu-case] viscous f32 rel L1 {err}", flush=True)
-    assert (err <= 1e-5).all()
+    print(f"[gpu-case] viscous {prec} rel L1 {err}", flush=True)
+    assert (err <= FORM_BOUND[prec]).all()
 
 
 def test_viscous_full_size_step_sampled():
@@ -173,7 +182,7 @@ def test_viscous_rejections():
     w = _viscous(CASES["mixed_70x9x7"]())
     banner("viscous rejections")
     with pytest.raises(igr.IGRError) as e:
-        igr.Solver.from_workload(w, precision="bf16")
+        igr.Solver.from_workload(w, precision="bf16d")
     assert e.value.code == igr.IGR_EUNSUPPORTED
     s = igr.Solver.from_workload(w)
     U = s.state_from(w.U)
