@@ -79,6 +79,49 @@ def test_viscous_steps(vcase):
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
 
 
+# degenerate extents: single planes, rows and columns (z chunks of one
+# plane, tiles narrower than a wave, halos reaching ghosts on both sides)
+DEGENERATE = {
+    "5x3x1_extrap": ((5, 3, 1), ("extrap",) * 6),
+    "1x7x4_periodic": ((1, 7, 4), ("periodic",) * 6),
+    "64x2x1_mixed": ((64, 2, 1), ("extrap", "extrap", "periodic", "periodic", "periodic", "periodic")),
+    "3x1x1_periodic": ((3, 1, 1), ("periodic",) * 6),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_viscous_degenerate_extents(name):
+    (nx, ny, nz), faces = DEGENERATE[name]
+    U0 = inputs.random_state(nx, ny, nz, 11, amp=0.3, umax=0.4)
+    dx = 1.0 / max(nx, ny, nz)
+    w = _viscous(inputs.Workload("degenerate", nx, ny, nz, dx, 1.1 * dx, 0.9 * dx, U0, alpha=0.7 * dx * dx,
+                                 faces=faces, jets=[], nsweeps=5))
+    banner(f"viscous degenerate extents {name}")
+    s = igr.Solver.from_workload(w)
+    prob = problem_from(w)
+    L = to_host(s, s.rhs(s.state_from(w.U), s.field_from(_sigma0(w))))
+    Lo, _ = ref.rhs(prob, torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)))
+    assert rel_linf(L, Lo.numpy()).max() <= TOL
+    # the viscous contribution alone, against its own size
+    w0 = _viscous(w, 0.0, 0.0)
+    s0 = igr.Solver.from_workload(w0)
+    L0 = to_host(s0, s0.rhs(s0.state_from(w.U), s0.field_from(_sigma0(w))))
+    Lo0, _ = ref.rhs(problem_from(w0), torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)))
+    dv, dvo = L - L0, (Lo - Lo0).numpy()
+    assert np.abs(dvo[1:]).max() > 0
+    assert np.abs(dv - dvo).max() <= 1e-10 * np.abs(dvo).max()
+    # two steps
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    Uo, so = torch.from_numpy(w.U.copy()), torch.from_numpy(_sigma0(w))
+    dt = 0.5 * ref.compute_dt(prob, Uo, 0.5)
+    for _ in range(2):
+        s.step(U, sig, dt_fixed=dt)
+        Uo, so = ref.rk3_step(prob, Uo, so, dt)
+    assert rel_linf(to_host(s, U), Uo.numpy()).max() <= TOL
+    assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_viscous_advance_with_cfl_matches_steps(prec):
     """With viscosity igr_advance takes each later time step from the CFL
