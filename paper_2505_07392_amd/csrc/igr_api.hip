@@ -581,10 +581,10 @@ long long flux_blocks(const igr_ctx* c) {
 // Viscous terms added to `out` (the right-hand side, or the stage the
 // flux kernel just wrote) from the stage input U: the stress, its ghosts,
 // then the tiled viscous flux divergence.  The plain forms.  Tile
-// heights (blocks of TY + 1 waves): FP64 7 (225 VGPRs at 2 waves per SIMD,
-// no spill; 1024^3: 50.3 ms per launch, against 72 ms with the face
-// stencils loaded whole and 108 ms without face sharing), FP32 11 (3 waves
-// per SIMD; 22.7 ms, TY = 8 about 4 ms more).  The stress kernel: 64 x 16 tiles
+// heights (blocks of TY + 1 waves): FP64 7 (220-231 VGPRs at 2 waves per
+// SIMD, no spill; 1024^3: 49.5-50.3 ms per launch, against 72 ms with the
+// face stencils loaded whole and 108 ms without face sharing), FP32 11 (3
+// waves per SIMD; 22.7 ms, TY = 8 about 4 ms more).  The stress kernel: 64 x 16 tiles
 // (1024^3 FP64 16.2 ms, FP32 12.5 ms; TY = 8 19.8 / 13.9 ms; a column
 // march without LDS 26.3 / 15.8 ms).
 #ifndef IGR_VISC_TY_F64
