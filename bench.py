@@ -95,12 +95,17 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":
         return 4 * eu + c          # rho, m read; b written
+    # rho, m of the stage input: the split form's later stages read U^n and
+    # a difference
+    state = 4 * (eu + ed * 2.0 / 3.0) if split else 4 * eu
     if kernel == "stress":
-        return 4 * eu + 6 * c      # rho, m read; the six stress components written
+        return state + 6 * c       # rho, m read; the six stress components written
     if kernel == "viscous":
         # rho, m and the six stress components read; the stage's four momentum
-        # and energy fields read and written
-        return 4 * eu + 6 * c + 8 * eu
+        # and energy fields read and written (split form: the differences of
+        # stages 1 and 2, U^(n+1) in stage 3)
+        out = (2 * 8 * ed + 8 * eu) / 3.0 if split else 8 * eu
+        return state + 6 * c + out
     if kernel == "dt":
         return 5 * eu
     raise KeyError(kernel)
@@ -301,7 +306,7 @@ def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None,
     six fields and the derived pressure against the FP64 run after
     `err_steps` steps from the initial state with one fixed dt (0.8 x the
     FP64 CFL step of the initial state).  mu, zeta: shear and bulk viscosity
-    of eq. (5) (the viscous terms run in the plain forms: not bf16d)."""
+    of eq. (5)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
@@ -377,7 +382,7 @@ def main():
     ap.add_argument("--order", type=int, default=5, choices=[5, 3], help="reconstruction order")
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "rbgs"], help="Sigma sweeps")
     ap.add_argument("--mu", type=float, default=0.0,
-                    help="shear viscosity of eq. (5) (viscous terms; plain storage forms, not bf16d)")
+                    help="shear viscosity of eq. (5) (viscous terms)")
     ap.add_argument("--zeta", type=float, default=0.0, help="bulk viscosity of eq. (5)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (calibrates HBM byte counters)")
@@ -387,8 +392,6 @@ def main():
               "design is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     viscous = args.mu > 0.0 or args.zeta > 0.0
-    if viscous and args.precision == "bf16d":
-        sys.exit("bench.py: the viscous terms run in the plain storage forms (f64, f32, f16, bf16), not bf16d")
 
     import torch
 
@@ -410,8 +413,6 @@ def main():
                           "seconds_per_copy": el, "GBs_read_plus_write": 2 * n * 8 / el / 1e9}))
         return
     forms_req = [x for x in args.forms.split(",") if x and x != args.precision]
-    if viscous:
-        forms_req = [f for f in forms_req if f != "bf16d"]
 
     if args.workload == "multi_jet":
         n = args.n or 1024

@@ -138,8 +138,7 @@ typedef struct {
     int32_t nsweeps;
     int32_t sigma_block;
     int32_t smoother;
-    double mu;     /* shear viscosity of eq. (5), >= 0 (0: the Euler system;
-                      > 0 or zeta > 0 needs a plain form, not IGR_F32_BF16D) */
+    double mu;     /* shear viscosity of eq. (5), >= 0 (0: the Euler system) */
     double zeta;   /* bulk viscosity of eq. (5), >= 0 */
 } igr_opts;
 

@@ -580,7 +580,7 @@ long long flux_blocks(const igr_ctx* c) {
 
 // Viscous terms added to `out` (the right-hand side, or the stage the
 // flux kernel just wrote) from the stage input U: the stress, its ghosts,
-// then the tiled viscous flux divergence.  The plain forms.  Tile
+// then the tiled viscous flux divergence.  Every form.  Tile
 // heights (blocks of TY + 1 waves): FP64 7 (220-231 VGPRs at 2 waves per
 // SIMD, no spill; 1024^3: 49.5-50.3 ms per launch, against 72 ms with the
 // face stencils loaded whole and 108 ms without face sharing), FP32 11 (3
@@ -622,12 +622,10 @@ long long visc_blocks(const igr_ctx* c) {
 
 // speed (last stage, nullable): the kernel also leaves the per-block CFL
 // maxima of the new state there (visc_blocks values).
-template <class F, int MODE>
-int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, const double* dtp, double dt_fixed,
-                 hipStream_t s, double* speed = nullptr) {
-    if constexpr (F::SPLIT) {
-        return fail(IGR_EUNSUPPORTED, "viscous terms need a plain storage form (not IGR_F32_BF16D)");
-    } else {
+template <class F, int MODE, bool HASD = false>
+int viscous_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, FluxOut<F, MODE>* out,
+                 const double* dtp, double dt_fixed, hipStream_t s, double* speed = nullptr) {
+    {
         using C = typename F::C;
         constexpr int TY = visc_ty<C>();
         constexpr int MW = sizeof(C) == 8 ? IGR_VISC_MINW_F64 : IGR_VISC_MINW_F32;
@@ -638,18 +636,18 @@ int viscous_impl(igr_ctx* c, const typename F::TB* U, FluxOut<F, MODE>* out, con
         const FluxLaunch LS = flux_launch(g, IGR_STRESS_TY, IGR_STRESS_BLOCKS);
         if (LS.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the stress launch");
         IGR_TRY(launch(c, K_STRESS, s, [&] {
-            k_stress<F, IGR_STRESS_TY><<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
-                U, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
+            k_stress<F, IGR_STRESS_TY, HASD><<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
+                U, D, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
         }));
         for (int q = 0; q < 6; ++q) IGR_TRY(fill_sigma_ghosts(c, T6 + (size_t)q * g.fs, s));
         return launch(c, K_VISCOUS, s, [&] {
             const dim3 grid(unsigned(L.blocks())), block(VISC_TX, TY + 1);
             if (c->order == 3)
-                k_viscous_tiled<F, MODE, TY, 3, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
-                                                                      L.tiles_y, L.zc, speed, c->d_flag);
+                k_viscous_tiled<F, MODE, TY, 3, MW, HASD><<<grid, block, 0, s>>>(
+                    U, D, T6, out, dtp, dt_fixed, g, L.tiles_x, L.tiles_y, L.zc, speed, c->d_flag);
             else
-                k_viscous_tiled<F, MODE, TY, 5, MW><<<grid, block, 0, s>>>(U, T6, out, dtp, dt_fixed, g, L.tiles_x,
-                                                                      L.tiles_y, L.zc, speed, c->d_flag);
+                k_viscous_tiled<F, MODE, TY, 5, MW, HASD><<<grid, block, 0, s>>>(
+                    U, D, T6, out, dtp, dt_fixed, g, L.tiles_x, L.tiles_y, L.zc, speed, c->d_flag);
         });
     }
 }
@@ -680,7 +678,7 @@ int rhs_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, typename F::TB*
     IGR_TRY(fill_state_ghosts(c, U, s));
     IGR_TRY(sigma_solve_impl<F>(c, U, sig, c->nsweeps, s));
     IGR_TRY((flux_impl<F, MODE_RHS>(c, U, nullptr, sig, nullptr, rhs, nullptr, 0.0, s)));
-    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_RHS>(c, U, rhs, nullptr, 0.0, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_RHS>(c, U, nullptr, rhs, nullptr, 0.0, s)));
     return IGR_OK;
 }
 
@@ -735,23 +733,25 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(solve(NoD{}, U, nullptr));
     }
     IGR_TRY((flux_impl<F, MODE_STAGE1>(c, U, nullptr, cur, nullptr, Ua, dtp, dt_fixed, s)));
-    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, Ua, dtp, dt_fixed, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, nullptr, Ua, dtp, dt_fixed, s)));
     if constexpr (F::SPLIT) {
         // stage 2: U2 - Un = 1/4 ((U1 - Un) + dt L(U1)), U1 = Un + Ua
         IGR_TRY(fill_state_ghosts(c, Ua, s, true));
         IGR_TRY(solve(LaterD{}, U, Ua));
         IGR_TRY((flux_impl<F, MODE_STAGE2, true>(c, U, Ua, cur, nullptr, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2, true>(c, U, Ua, Ub, dtp, dt_fixed, s)));
         // stage 3: Un+1 = Un + 2/3 ((U2 - Un) + dt L(U2)), U2 = Un + Ub
         IGR_TRY(fill_state_ghosts(c, Ub, s, true));
         IGR_TRY(solve(LaterD{}, U, Ub));
-        IGR_TRY((flux_impl<F, MODE_STAGE3, true>(c, U, Ub, cur, nullptr, Unew, dtp, dt_fixed, s, speed,
-                                                 cur != sig ? sig : nullptr)));
+        IGR_TRY((flux_impl<F, MODE_STAGE3, true>(c, U, Ub, cur, nullptr, Unew, dtp, dt_fixed, s,
+                                                 c->viscous ? nullptr : speed, cur != sig ? sig : nullptr)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3, true>(c, U, Ub, Unew, dtp, dt_fixed, s, speed)));
     } else {
         // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
         IGR_TRY(fill_state_ghosts(c, Ua, s));
         IGR_TRY(solve(NoD{}, Ua, nullptr));
         IGR_TRY((flux_impl<F, MODE_STAGE2>(c, Ua, nullptr, cur, U, Ub, dtp, dt_fixed, s)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, nullptr, Ub, dtp, dt_fixed, s)));
         // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
         // solve ended in the scratch copy the kernel also writes Sigma's interior
         // into the caller's buffer (its ghosts are scratch)
@@ -761,7 +761,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         // forms the CFL maxima instead of the flux kernel
         IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s,
                                            c->viscous ? nullptr : speed, cur != sig ? sig : nullptr)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, Unew, dtp, dt_fixed, s, speed)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s, speed)));
     }
     return IGR_OK;
 }
@@ -1223,8 +1223,6 @@ int igr_init(const igr_grid* grid, double gamma, double alpha, const igr_bc* bc,
     if (opts->precision == IGR_F32_BF16D && opts->sigma_block > 2)
         return fail(IGR_EUNSUPPORTED, "IGR_F32_BF16D runs single or two-sweep Sigma passes (sigma_block 0..2)");
     if (!(opts->mu >= 0.0) || !(opts->zeta >= 0.0)) return fail(IGR_EINVAL, "viscosities must be >= 0");
-    if ((opts->mu > 0.0 || opts->zeta > 0.0) && opts->precision == IGR_F32_BF16D)
-        return fail(IGR_EUNSUPPORTED, "viscous terms need a plain storage form (not IGR_F32_BF16D)");
     if (opts->order != 5 && opts->order != 3)
         return fail(IGR_EUNSUPPORTED, "reconstruction order must be 5 or 3");
     if (opts->nsweeps < 0) return fail(IGR_EINVAL, "nsweeps must be >= 0");

@@ -53,12 +53,12 @@ __host__ __device__ constexpr int tau_index(int a, int b) {
 // is fetched while plane k is processed), so that each input value is read
 // from HBM about once.
 constexpr int STRESS_TX = 64;
-template <class F, int TY>
+template <class F, int TY, bool HASD>
 __global__ __launch_bounds__(STRESS_TX* TY) void k_stress(const typename F::TB* __restrict__ U,
+                                                          const typename F::TD* __restrict__ D,
                                                           typename F::C* __restrict__ T6, Geom g, double mu_,
                                                           double zeta_, int tiles_x, int tiles_y, int zc) {
     using C = typename F::C;
-    using SU = Storage<typename F::TB>;
     constexpr int TX = STRESS_TX;
     static_assert(TX * TY <= 1024, "at most 1024 threads per block");
     __shared__ C pl[4][TY + 2][TX + 2];
@@ -78,9 +78,11 @@ __global__ __launch_bounds__(STRESS_TX* TY) void k_stress(const typename F::TB* 
     const bool col_load = i < nx + 1 && j < ny + 1;
     const bool col_out = i < nx && j < ny;
     const uint32_t col = uint32_t((j + G) * sy + (i + G));
+    // the stage input (U, + its difference D in the split form's later stages)
     auto ld = [&](int f, int plane, uint32_t o) -> C {
         plane = __builtin_amdgcn_readfirstlane(plane);
-        return C(SU::load(at_plane(U + ((long long)f * fs + (long long)(plane + G) * sz), o)));
+        const long long po = (long long)f * fs + (long long)(plane + G) * sz;
+        return F::cvt(F::template load_up<HASD>(U + po, HASD ? D + po : nullptr, o));
     };
     // rho, m_x, m_y, m_z of planes k-1 (qm), k (q0), k+1 (qp), k+2 (nxt)
     // after the shift at the top of iteration k
@@ -245,10 +247,12 @@ constexpr int VISC_TX = 64;
 // tau_yy, tau_zy)
 constexpr int VISC_NF = 9;
 
-// F: a plain storage form (FP64, FP32, or 16-bit storage with FP32
-// arithmetic: the stage output that the flux kernel rounded to storage is
-// read back, the viscous increment added in FP32, and the sum rounded
-// again).  U: the stage input (ghosts filled);
+// F: a storage form (FP64, FP32, 16-bit storage with FP32 arithmetic, or
+// the split form; where the stage output is stored in fewer bits than the
+// arithmetic, the value the flux kernel rounded is read back, the viscous
+// increment added in FP32 and the sum rounded again: in the split form's
+// stages 1 and 2 that value is the BF16 difference from U^n).  U (+ D with
+// HASD, the split form's later stages): the stage input (ghosts filled);
 // T6: its stress (ghosts filled); out: the stage output that the flux
 // kernel wrote (or the right-hand side), read and written pointwise.
 // speed (last stage, nullable): one CFL maximum per block of the new state
@@ -257,8 +261,9 @@ constexpr int VISC_NF = 9;
 // Block: 64 x (TY + 1) threads; wave w < TY owns row w of the tile, wave
 // TY computes the extra row of y faces and the x faces at the tile's left
 // edge.  All faces of one direction run through one instruction sequence.
-template <class F, int MODE, int TY, int ORDER, int MINW>
+template <class F, int MODE, int TY, int ORDER, int MINW, bool HASD>
 __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const typename F::TB* __restrict__ U,
+                                                                           const typename F::TD* __restrict__ D,
                                                                            const typename F::C* __restrict__ T6,
                                                                            FluxOut<F, MODE>* out,
                                                                            const double* __restrict__ dtp,
@@ -307,13 +312,14 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
         return a + ((long long)f * fs + (long long)(plane + G) * sz);
     };
     auto ldf = [&](int f, int plane, uint32_t o) -> C {
-        if constexpr (std::is_same_v<typename F::TB, C>) {
+        if constexpr (!F::SPLIT && std::is_same_v<typename F::TB, C>) {
             // FP64 / FP32: one load through a selected base
             const C* a = f < 4 ? U + (long long)f * fs : T6 + (long long)(f - 4) * fs;
             return SU::load(at_plane(plane_of(a, 0, plane), o));
         } else {
-            // 16-bit state, FP32 stress
-            if (f < 4) return C(SU::load(at_plane(plane_of(U, f, plane), o)));
+            // 16-bit state, or the split form's U^n (+ difference); FP32 stress
+            if (f < 4)
+                return F::cvt(F::template load_up<HASD>(plane_of(U, f, plane), HASD ? plane_of(D, f, plane) : nullptr, o));
             return *at_plane(plane_of(T6, f - 4, plane), o);
         }
     };

@@ -57,7 +57,7 @@ def _init(grid, gamma, alpha, bc, opts):
     ("sweeps", igr.IGR_EINVAL), ("spacing", igr.IGR_EINVAL), ("sigma_block", igr.IGR_EINVAL),
     ("smoother", igr.IGR_EINVAL), ("rbgs_odd_periodic", igr.IGR_EUNSUPPORTED),
     ("plane_too_large", igr.IGR_EINVAL), ("split_march", igr.IGR_EUNSUPPORTED),
-    ("negative_mu", igr.IGR_EINVAL), ("viscous_split", igr.IGR_EUNSUPPORTED),
+    ("negative_mu", igr.IGR_EINVAL), ("negative_zeta", igr.IGR_EINVAL),
 ])
 def test_init_rejects_bad_arguments(case, code):
     grid, bc, opts, gamma, alpha = _grid(), _bc(), igr.Opts(0, 5, 5, 0), 1.4, 0.01
@@ -93,8 +93,8 @@ def test_init_rejects_bad_arguments(case, code):
         opts = igr.Opts(4, 5, 5, 3)   # the split form runs single or two-sweep passes only
     elif case == "negative_mu":
         opts = igr.Opts(0, 5, 5, 0, 0, -1e-3, 0.0)
-    elif case == "viscous_split":
-        opts = igr.Opts(4, 5, 5, 0, 0, 1e-3, 0.0)     # viscous terms: plain storage forms only
+    elif case == "negative_zeta":
+        opts = igr.Opts(0, 5, 5, 0, 0, 1e-3, -1e-3)
     rc, h = _init(grid, gamma, alpha, bc, opts)
     assert rc == code
     assert h.value is None

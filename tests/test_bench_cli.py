@@ -25,12 +25,6 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU only" in r.stderr
 
 
-def test_viscous_terms_need_a_plain_form():
-    r = _run("--mu", "1e-5", "--precision", "bf16d")
-    assert r.returncode != 0
-    assert "plain storage forms" in r.stderr
-
-
 def test_byte_model():
     """Values per cell: flux stage 1 reads U and Sigma and writes U (11),
     stages 2 and 3 also read U^n (16); the stress reads rho and m and writes
@@ -42,6 +36,10 @@ def test_byte_model():
     assert bench.algorithmic_bytes_per_cell("stress", "f32", 10) == 4 * 10
     assert bench.algorithmic_bytes_per_cell("viscous", "f64", 10) == 8 * 18
     assert bench.algorithmic_bytes_per_cell("viscous", "f32", 10) == 4 * 18
+    # split form: FP32 U^n, BF16 differences; rho, m of stages 2 and 3 read
+    # both, the outputs of stages 1 and 2 are differences
+    assert bench.algorithmic_bytes_per_cell("stress", "bf16d", 10) == 4 * (4 + 2 * 2 / 3) + 6 * 4
+    assert bench.algorithmic_bytes_per_cell("viscous", "bf16d", 10) == 4 * (4 + 2 * 2 / 3) + 6 * 4 + (2 * 16 + 32) / 3
     with pytest.raises(KeyError):
         bench.algorithmic_bytes_per_cell("nonesuch", "f64", 10)
 
