@@ -299,14 +299,15 @@ def _final_fields(s, U, S, gamma):
 
 
 def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None, mu: float = 0.0,
-               zeta: float = 0.0):
+               zeta: float = 0.0, order: int = 5, sigma_block: int = 0, smoother: str = "jacobi"):
     """Multi-jet box in each precision form (FP64 first): the rate over
     `steps` CFL steps after `warmup` (igr_advance, HIP-event timing of every
     launch), the device memory in use, and the per-field rel L1 error of the
     six fields and the derived pressure against the FP64 run after
     `err_steps` steps from the initial state with one fixed dt (0.8 x the
     FP64 CFL step of the initial state).  mu, zeta: shear and bulk viscosity
-    of eq. (5)."""
+    of eq. (5); order, sigma_block, smoother: the solver options (0: the
+    library's default pass structure)."""
     import torch
 
     from paper_2505_07392_amd import igr, inputs
@@ -317,7 +318,7 @@ def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None,
     out, ref, dt = {}, None, None
     for prec in forms:
         say(f"[bench] multi-jet {n}^3 {prec}: building the state")
-        s = igr.Solver.from_workload(w, precision=prec)
+        s = igr.Solver.from_workload(w, precision=prec, order=order, sigma_block=sigma_block, smoother=smoother)
         U = s.new_state()
         inputs.fill_multi_jet_state(w, s.interior(U))
         S = s.new_field()
@@ -339,7 +340,7 @@ def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None,
         form = {"value": w.cells * steps / el, "ms_per_step": 1e3 * el / steps, "elapsed_s": el,
                 "device_bytes_in_use": total - free, "frac_of_288GB": round((total - free) / 288e9, 4),
                 "sigma_block": s.sigma_block, "kernel_times": kt}
-        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block))
+        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block, smoother))
         if err_steps > 0:
             say(f"[bench] multi-jet {n}^3 {prec}: {err_steps} fixed-dt steps for the error")
             inputs.fill_multi_jet_state(w, s.interior(U))
@@ -417,7 +418,8 @@ def main():
     if args.workload == "multi_jet":
         n = args.n or 1024
         w, res, dt_err = jets_forms(n, [args.precision] + forms_req, args.steps, args.warmup, args.err_steps,
-                                    mu=args.mu, zeta=args.zeta)
+                                    mu=args.mu, zeta=args.zeta, order=args.order, sigma_block=args.sigma_block,
+                                    smoother=args.smoother)
         main_form = res.pop(args.precision)
         cells, el, kt, sb = w.cells, main_form["elapsed_s"], main_form.pop("kernel_times"), main_form["sigma_block"]
         workload = f"multi_jet_{n}"

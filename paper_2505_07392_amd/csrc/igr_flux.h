@@ -2,9 +2,9 @@
 //
 // One block owns a 64 x TY column tile of the x-y plane and marches through
 // a chunk of z planes.  For each plane k:
-//   A  the plane (six fields rho, m, E, Sigma, with a three-cell x/y halo)
-//      is staged in LDS: interior cells from the register queue of each
-//      thread's column, halo cells from global memory (L2);
+//   A  the plane (six fields rho, m, E, Sigma, with a three-cell x/y halo;
+//      two for third order) is staged in LDS: interior cells from the
+//      register queue of each thread's column, halo cells from global memory;
 //   B  every face is computed once: x faces (i+1/2) and y faces (j-1/2)
 //      from the LDS plane, the z face (k+1/2) from the column's register
 //      queue of planes k-2..k+3; x/y face fluxes go to LDS;
@@ -71,8 +71,14 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     using SO = Storage<FluxOut<F, MODE>>;
     using SS = Storage<typename F::TS>;
     constexpr int TX = FLUX_TX;
-    constexpr int W = TX + 2 * G;
-    constexpr int H = TY + 2 * G;
+    // LDS halo width: the reconstruction's reach (three cells, two for
+    // third order; the arrays keep G ghost layers either way).  A face's
+    // six-cell window v[0..5] (cells -3..+2 around it) is read from LDS
+    // for the slots the reconstruction uses, PO..5-PO.
+    constexpr int HG = ORDER == 5 ? G : 2;
+    constexpr int PO = G - HG;
+    constexpr int W = TX + 2 * HG;
+    constexpr int H = TY + 2 * HG;
     __shared__ C pl[6][H][W];
     __shared__ C fx[5][TY][TX + 1];
     __shared__ C fy[5][TY + 1][TX];
@@ -173,30 +179,30 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
     }
 
     // halo of the next plane, prefetched into registers.  Regular pattern:
-    // the y-halo (2G rows x TX columns x 6 fields) goes row by row to the
-    // waves (lane = column, coalesced); the x-halo (2G columns x TY rows x
-    // 6 fields) to the first 6 * 2G * TY threads.
+    // the y-halo (2 HG rows x TX columns x 6 fields) goes row by row to the
+    // waves (lane = column, coalesced); the x-halo (2 HG columns x TY rows x
+    // 6 fields) to the first 6 * 2 HG * TY threads.
     constexpr int NW = TY + 1;                   // waves per block
-    constexpr int NYR = 6 * 2 * G;               // y-halo rows over all fields
+    constexpr int NYR = 6 * 2 * HG;              // y-halo rows over all fields
     constexpr int HY = (NYR + NW - 1) / NW;      // y-halo rows per wave
-    constexpr int NXH = 6 * 2 * G * TY;          // x-halo cells over all fields
+    constexpr int NXH = 6 * 2 * HG * TY;         // x-halo cells over all fields
     RU hy[HY], hx = RU{};
     auto y_slot = [&](int s, int& f, int& cy) -> bool {
         const int rf = wv + s * NW;
         if (rf >= NYR) return false;
-        f = rf / (2 * G);
-        const int rr = rf - f * 2 * G;
-        cy = rr < G ? rr - G : TY + (rr - G);
+        f = rf / (2 * HG);
+        const int rr = rf - f * 2 * HG;
+        cy = rr < HG ? rr - HG : TY + (rr - HG);
         const int gy = y0 + cy;
         return (x0 + lane) < nx + G && gy >= -G && gy < ny + G;
     };
     auto x_slot = [&](int& f, int& cx, int& cy) -> bool {
         if (tid >= NXH) return false;
-        f = tid / (2 * G * TY);
-        const int r = tid - f * 2 * G * TY;
-        cy = r / (2 * G);
-        const int c = r - cy * 2 * G;
-        cx = c < G ? c - G : TX + (c - G);
+        f = tid / (2 * HG * TY);
+        const int r = tid - f * 2 * HG * TY;
+        cy = r / (2 * HG);
+        const int c = r - cy * 2 * HG;
+        cx = c < HG ? c - HG : TX + (c - HG);
         const int gx = x0 + cx;
         return gx >= -G && gx < nx + G && (y0 + cy) < ny + G;
     };
@@ -271,16 +277,16 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
             // prefetched registers), then prefetch the halo of plane k+1
             if (own) {
 #pragma unroll
-                for (int f = 0; f < 6; ++f) pl[f][wv + G][lane + G] = q[f][2];
+                for (int f = 0; f < 6; ++f) pl[f][wv + HG][lane + HG] = q[f][2];
             }
 #pragma unroll
             for (int s = 0; s < HY; ++s) {
                 int f, cy;
-                if (y_slot(s, f, cy)) pl[f][cy + G][lane + G] = F::cvt(hy[s]);
+                if (y_slot(s, f, cy)) pl[f][cy + HG][lane + HG] = F::cvt(hy[s]);
             }
             {
                 int f, cx, cy;
-                if (x_slot(f, cx, cy)) pl[f][cy + G][cx + G] = F::cvt(hx);
+                if (x_slot(f, cx, cy)) pl[f][cy + HG][cx + HG] = F::cvt(hx);
             }
             if (k + 1 < z1) load_halo(k + 1);
             __syncthreads();
@@ -300,7 +306,8 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                         for (int f = 0; f < 6; ++f)
 #pragma unroll
-                            for (int p = 0; p < 6; ++p) v[f][p] = pl[f][r + G][fi + p];
+                            for (int p = 0; p < 6; ++p)
+                                v[f][p] = (p >= PO && p < 6 - PO) ? pl[f][r + HG][fi + p - PO] : C(0);
                         C Fl[5];
                         face_flux6<C, ORDER>(v, 0, gamma, Fl, bad);
 #pragma unroll
@@ -316,7 +323,8 @@ __global__ __launch_bounds__(FLUX_TX*(TY + 1)) void k_flux_tiled(
 #pragma unroll
                         for (int f = 0; f < 6; ++f)
 #pragma unroll
-                            for (int p = 0; p < 6; ++p) v[f][p] = pl[f][wv + p][lane + G];
+                            for (int p = 0; p < 6; ++p)
+                                v[f][p] = (p >= PO && p < 6 - PO) ? pl[f][wv + p - PO][lane + HG] : C(0);
                         C Fl[5];
                         face_flux6<C, ORDER>(v, 1, gamma, Fl, bad);
 #pragma unroll
