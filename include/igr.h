@@ -210,8 +210,9 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
 int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,
                 void *stream);
 
-/* Discrete adjoint of igr_rhs (FP64 contexts with fifth-order
- * reconstruction, else IGR_EUNSUPPORTED; vector-Jacobian product of
+/* Discrete adjoint of igr_rhs (FP64 contexts with Jacobi sweeps and no
+ * viscous terms, either reconstruction order, else IGR_EUNSUPPORTED;
+ * vector-Jacobian product of
  * the map (U, sigma_prev) -> (L(U), sigma_new) and of the jet-disc
  * states).  Given rhs_bar (5 fields) and sigma_bar (cotangent of the new
  * Sigma), writes U_bar (5 fields) and sigma_prev_bar; only interiors are
@@ -224,8 +225,8 @@ int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, 
 int igr_rhs_adjoint(igr_ctx *ctx, void *U, const void *sigma_prev, const void *rhs_bar, const void *sigma_bar,
                     void *U_bar, void *sigma_prev_bar, double *patch_bar, void *stream);
 
-/* Discrete adjoint of one igr_step with a fixed time step dt > 0 (FP64,
- * fifth-order reconstruction):
+/* Discrete adjoint of one igr_step with a fixed time step dt > 0 (the
+ * contexts igr_rhs_adjoint accepts):
  * given the step's input (U_n, sigma_n) and the cotangents of its output
  * (U_bar_np1, sigma_bar_np1), writes the cotangents of its input (U_bar_n,
  * sigma_bar_n) and, if patch_bar is not NULL, of the primitive jet states

@@ -85,7 +85,7 @@ __device__ __forceinline__ void side_reverse(const SideFwd& v, int d, double gam
     Ub[0] -= irb * v.ir * v.ir;
 }
 
-template <int D>
+template <int D, int ORDER>
 __global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ U, const double* __restrict__ Sg,
                                                   const double* __restrict__ Lb, double* __restrict__ FA, Geom g) {
     const Line tl = transverse(D);
@@ -118,10 +118,17 @@ __global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ U, 
     }
     SideFwd L, R;
     double UL[5], UR[5];
-    for (int k = 0; k < 5; ++k) {
-        UL[k] = recon_left(q[k][0], q[k][1], q[k][2], q[k][3], q[k][4]);
-        UR[k] = recon_right(q[k][1], q[k][2], q[k][3], q[k][4], q[k][5]);
-    }
+    // cells l-2..l+3 in q[.][0..5]; third order reads l-1..l+2
+    auto rec = [&](const double (&v)[6], double& l, double& r) {
+        if constexpr (ORDER == 5) {
+            l = recon_left(v[0], v[1], v[2], v[3], v[4]);
+            r = recon_right(v[1], v[2], v[3], v[4], v[5]);
+        } else {
+            l = recon3_left(v[1], v[2], v[3]);
+            r = recon3_right(v[2], v[3], v[4]);
+        }
+    };
+    for (int k = 0; k < 5; ++k) rec(q[k], UL[k], UR[k]);
     L.rho = UL[0];
     R.rho = UR[0];
     for (int k = 0; k < 3; ++k) {
@@ -130,8 +137,7 @@ __global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ U, 
     }
     L.E = UL[4];
     R.E = UR[4];
-    L.S = recon_left(q[5][0], q[5][1], q[5][2], q[5][3], q[5][4]);
-    R.S = recon_right(q[5][1], q[5][2], q[5][3], q[5][4], q[5][5]);
+    rec(q[5], L.S, R.S);
     side_forward(L, D, gamma);
     side_forward(R, D, gamma);
     const double lam = fmax(L.s, R.s);
@@ -182,7 +188,10 @@ __global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ U, 
 
 // Transposed reconstruction: padded cell q along D (q = -3..n+2) gathers
 // from the faces whose stencils contain it; adds into Ub (5) and Sb.
-template <int D>
+// Fifth order: the left state of face l+1/2 weighs cells l-2..l+2 by
+// (2, -13, 47, 27, -3)/60, the right state l-1..l+3 by the mirror image;
+// third order: l-1..l+1 by (-1, 5, 2)/6 and l..l+2 by (2, 5, -1)/6.
+template <int D, int ORDER>
 __global__ __launch_bounds__(256) void k_adj_recon_gather(const double* __restrict__ FA, double* __restrict__ Ub,
                                                           double* __restrict__ Sb, Geom g) {
     const Line tl = transverse(D);
@@ -197,23 +206,27 @@ __global__ __launch_bounds__(256) void k_adj_recon_gather(const double* __restri
     const int ib = int(line / g.n[tl.a]);
     const int sd = g.st[D];
     const long long base = (long long)(ia + G) * g.st[tl.a] + (long long)(ib + G) * g.st[tl.b];
-    const double CLc[5] = {2.0, -13.0, 47.0, 27.0, -3.0};
-    const double CRc[5] = {-3.0, 27.0, 47.0, -13.0, 2.0};
+    constexpr int NS = ORDER == 5 ? 5 : 3;                 // cells per one-sided stencil
+    constexpr int SL = ORDER == 5 ? 2 : 1;                 // left state: cells l-SL .. l-SL+NS-1
+    constexpr int SR = ORDER == 5 ? 1 : 0;                 // right state: cells l-SR ..
+    constexpr double DEN = ORDER == 5 ? 60.0 : 6.0;
+    const double CLc[5] = {ORDER == 5 ? 2.0 : -1.0, ORDER == 5 ? -13.0 : 5.0, ORDER == 5 ? 47.0 : 2.0, 27.0, -3.0};
+    const double CRc[5] = {ORDER == 5 ? -3.0 : 2.0, ORDER == 5 ? 27.0 : 5.0, ORDER == 5 ? 47.0 : -1.0, -13.0, 2.0};
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int m = 0; m < 5; ++m) {
-        // left state of face l uses cells l-2..l+2: cell qp = l - 2 + m
-        const int lL = qp + 2 - m;
+    for (int m = 0; m < NS; ++m) {
+        // left state of face l: cell qp = l - SL + m
+        const int lL = qp + SL - m;
         if (lL >= -1 && lL <= nd - 1) {
             const long long of = base + (long long)(lL + 1 + G) * sd;
-            const double w = CLc[m] / 60.0;
+            const double w = CLc[m] / DEN;
             for (int k = 0; k < 5; ++k) acc[k] += w * FA[k * g.fs + of];
             acc[5] += w * FA[10 * g.fs + of];
         }
-        // right state of face l uses cells l-1..l+3: cell qp = l - 1 + m
-        const int lR = qp + 1 - m;
+        // right state of face l: cell qp = l - SR + m
+        const int lR = qp + SR - m;
         if (lR >= -1 && lR <= nd - 1) {
             const long long of = base + (long long)(lR + 1 + G) * sd;
-            const double w = CRc[m] / 60.0;
+            const double w = CRc[m] / DEN;
             for (int k = 0; k < 5; ++k) acc[k] += w * FA[(5 + k) * g.fs + of];
             acc[5] += w * FA[11 * g.fs + of];
         }

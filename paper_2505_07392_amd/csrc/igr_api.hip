@@ -1051,16 +1051,23 @@ int stage_adjoint(igr_ctx* c, double* U, const double* Sp, const double* Lb, con
         const long long lines = (long long)g.n[a] * g.n[b];
         const int bf = int((lines * (g.n[d] + 1) + 255) / 256);
         const int bg = int((lines * (g.n[d] + 2 * G) + 255) / 256);
+        auto faces = [&](auto dd, auto order) {
+            constexpr int DD = decltype(dd)::value, OR = decltype(order)::value;
+            k_adj_face<DD, OR><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
+            k_adj_recon_gather<DD, OR><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+        };
         IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+            using O3 = std::integral_constant<int, 3>;
+            using O5 = std::integral_constant<int, 5>;
             if (d == 0) {
-                k_adj_face<0><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
-                k_adj_recon_gather<0><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+                if (c->order == 3) faces(std::integral_constant<int, 0>{}, O3{});
+                else faces(std::integral_constant<int, 0>{}, O5{});
             } else if (d == 1) {
-                k_adj_face<1><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
-                k_adj_recon_gather<1><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+                if (c->order == 3) faces(std::integral_constant<int, 1>{}, O3{});
+                else faces(std::integral_constant<int, 1>{}, O5{});
             } else {
-                k_adj_face<2><<<bf, 256, 0, s>>>(U, Spad, Lb, FA, g);
-                k_adj_recon_gather<2><<<bg, 256, 0, s>>>(FA, Ubpad, Sbpad, g);
+                if (c->order == 3) faces(std::integral_constant<int, 2>{}, O3{});
+                else faces(std::integral_constant<int, 2>{}, O5{});
             }
         }));
     }
@@ -1500,7 +1507,6 @@ int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* r
     if (!ctx || !U || !sigma_prev || !rhs_bar || !sigma_bar || !U_bar || !sigma_prev_bar)
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
-    if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
     if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     hipStream_t s = as_stream(stream);
@@ -1527,7 +1533,6 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     if (!ctx || !U_n || !sigma_n || !U_bar_np1 || !sigma_bar_np1 || !U_bar_n || !sigma_bar_n)
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
-    if (ctx->order != 5) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for fifth-order reconstruction");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
     if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");

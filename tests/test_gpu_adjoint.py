@@ -1,8 +1,9 @@
 """GPU checks of the hand-written adjoint (FP64).
 
 * igr_rhs_adjoint and igr_step_adjoint against the oracle's discrete
-  adjoint (torch.autograd through oracle/igr_ref.py) on the same inputs:
-  cotangents of U, of the warm-start Sigma and of the jet pressures.
+  adjoint (torch.autograd through oracle/igr_ref.py) on the same inputs,
+  with fifth- and third-order reconstruction: cotangents of U, of the
+  warm-start Sigma and of the jet pressures.
 * Transposition: <J v, w> computed by central differences of the GPU
   forward equals <v, J^T w> from the adjoint.
 * The 128^3 gradient workload (2 x 2 Mach-2 jets, 40 fixed-dt steps,
@@ -49,8 +50,8 @@ def _rel(got, want):
     return float(np.abs(got - want).max() / scale) if scale > 0 else float(np.abs(got).max())
 
 
-def _oracle_problem(w, p_tensor=None):
-    prob = problem_from(w)
+def _oracle_problem(w, p_tensor=None, order=5):
+    prob = problem_from(w, order=order)
     if p_tensor is not None:
         for i, pa in enumerate(prob.patches):
             pa.p = p_tensor[i]
@@ -65,21 +66,22 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("order", [5, 3])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_rhs_adjoint_matches_oracle_autograd(name):
+def test_rhs_adjoint_matches_oracle_autograd(name, order):
     w = CASES[name]()
-    banner(f"rhs adjoint {name}")
+    banner(f"rhs adjoint {name} order {order}")
     rng = np.random.default_rng(5)
     sig0 = rng.random((w.nz, w.ny, w.nx)) * 0.1
     Lbar = rng.standard_normal((5, w.nz, w.ny, w.nx))
     Sbar = rng.standard_normal((w.nz, w.ny, w.nx))
-    s = igr.Solver.from_workload(w)
+    s = igr.Solver.from_workload(w, order=order)
     Ub, Sb, pb = s.rhs_adjoint(s.state_from(w.U), s.field_from(sig0), s.state_from(Lbar), s.field_from(Sbar))
     # oracle autograd
     U = torch.from_numpy(w.U.copy()).requires_grad_(True)
     S0 = torch.from_numpy(sig0).requires_grad_(True)
     p = torch.tensor([j.p for j in w.jets], dtype=torch.float64, requires_grad=True)
-    prob = _oracle_problem(w, p if w.jets else None)
+    prob = _oracle_problem(w, p if w.jets else None, order)
     L, Sn = ref.rhs(prob, U, S0)
     inputs_ = [U, S0] + ([p] if w.jets else [])
     grads = torch.autograd.grad((L, Sn), inputs_, (torch.from_numpy(Lbar), torch.from_numpy(Sbar)),
@@ -91,20 +93,21 @@ def test_rhs_adjoint_matches_oracle_autograd(name):
         assert abs(pb[0, 4].item() - grads[2][0].item()) <= ADJ_TOL * abs(grads[2][0].item())
 
 
-def test_step_adjoint_matches_oracle_autograd():
+@pytest.mark.parametrize("order", [5, 3])
+def test_step_adjoint_matches_oracle_autograd(order):
     w = _case(16, 8, 6, seed=3)
-    banner("step adjoint vs oracle autograd")
+    banner(f"step adjoint vs oracle autograd, order {order}")
     rng = np.random.default_rng(6)
     sig0 = rng.random((w.nz, w.ny, w.nx)) * 0.1
     Ubar = rng.standard_normal((5, w.nz, w.ny, w.nx))
     Sbar = rng.standard_normal((w.nz, w.ny, w.nx))
     dt = 0.3 * ref.compute_dt(problem_from(w), torch.from_numpy(w.U), 0.5)
-    s = igr.Solver.from_workload(w)
+    s = igr.Solver.from_workload(w, order=order)
     Ub, Sb, pb = s.step_adjoint(s.state_from(w.U), s.field_from(sig0), dt, s.state_from(Ubar), s.field_from(Sbar))
     U = torch.from_numpy(w.U.copy()).requires_grad_(True)
     S0 = torch.from_numpy(sig0).requires_grad_(True)
     p = torch.tensor([j.p for j in w.jets], dtype=torch.float64, requires_grad=True)
-    U1, S1 = ref.rk3_step(_oracle_problem(w, p), U, S0, dt)
+    U1, S1 = ref.rk3_step(_oracle_problem(w, p, order), U, S0, dt)
     gU, gS, gp = torch.autograd.grad((U1, S1), (U, S0, p), (torch.from_numpy(Ubar), torch.from_numpy(Sbar)))
     for f in range(5):
         assert _rel(to_host(s, Ub)[f], gU[f].numpy()) <= ADJ_TOL, f
@@ -217,18 +220,6 @@ def test_gradient_workload_128_against_finite_differences(plane):
 
 def Solver_interior(a):
     return igr.Solver.interior(a)
-
-
-def test_adjoint_rejects_third_order():
-    """The hand-written adjoint covers fifth-order reconstruction only; a
-    third-order context reports IGR_EUNSUPPORTED instead of a wrong result."""
-    w = _case()
-    s = igr.Solver.from_workload(w, order=3)
-    U = s.state_from(w.U)
-    sig = s.new_field()
-    with pytest.raises(igr.IGRError) as e:
-        s.rhs_adjoint(U, sig, torch.zeros_like(U), torch.zeros_like(sig))
-    assert e.value.code == igr.IGR_EUNSUPPORTED
 
 
 def test_adjoint_rejects_red_black():
