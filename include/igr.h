@@ -210,9 +210,9 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
 int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,
                 void *stream);
 
-/* Discrete adjoint of igr_rhs (FP64 contexts with Jacobi sweeps and no
- * viscous terms, either reconstruction order, else IGR_EUNSUPPORTED;
- * vector-Jacobian product of
+/* Discrete adjoint of igr_rhs (FP64 contexts with Jacobi sweeps, either
+ * reconstruction order, with or without the viscous terms, else
+ * IGR_EUNSUPPORTED; vector-Jacobian product of
  * the map (U, sigma_prev) -> (L(U), sigma_new) and of the jet-disc
  * states).  Given rhs_bar (5 fields) and sigma_bar (cotangent of the new
  * Sigma), writes U_bar (5 fields) and sigma_prev_bar; only interiors are

@@ -973,6 +973,10 @@ enum AdjBuf {
     A_NB = A_FA + 12, A_DB, A_BB, A_IR, A_IRB, A_LB, A_UST = A_LB + 5, A_SBA = A_UST + 5, A_SBB, A_UBN,
     A_UB1 = A_UBN + 5, A_UB2 = A_UB1 + 5, A_UBIN = A_UB2 + 5, A_SBIN = A_UBIN + 5, A_ITER
 };
+// Viscous adjoint scratch (a second block, viscous contexts only): face
+// cotangents (14), tau-bar with ghosts (6), folded tau-bar (6), G-bar (9),
+// a field of zeros
+enum ViscAdjBuf { V_FV, V_TB = V_FV + 14, V_TF = V_TB + 6, V_GB = V_TF + 6, V_ZERO = V_GB + 9, V_COUNT };
 
 int adjoint_buffers(igr_ctx* c) {
     const int S = c->nsweeps;
@@ -988,11 +992,21 @@ int adjoint_buffers(igr_ctx* c) {
                                      std::string("adjoint scratch: ") + hipGetErrorString(e));
     c->adj.push_back(base);
     IGR_HIP(hipMemset(base, 0, (size_t)nfield * field_bytes(c, sizeof(double))));
+    if (c->viscous) {
+        double* vb = nullptr;
+        e = hipMalloc((void**)&vb, (size_t)V_COUNT * field_bytes(c, sizeof(double)));
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? IGR_ENOMEM : IGR_EHIP,
+                                         std::string("viscous adjoint scratch: ") + hipGetErrorString(e));
+        c->adj.push_back(vb);
+        IGR_HIP(hipMemset(vb, 0, (size_t)V_COUNT * field_bytes(c, sizeof(double))));
+    }
     c->adj_sweeps = S;
     return IGR_OK;
 }
 
 double* abuf(igr_ctx* c, int idx) { return c->adj[0] + (size_t)idx * c->g.fs; }
+
+double* vbuf(igr_ctx* c, int idx) { return c->adj[1] + (size_t)idx * c->g.fs; }
 double* ajetcol(igr_ctx* c) { return c->adj[0] + (size_t)(A_ITER + c->nsweeps + 1) * c->g.fs; }
 
 dim3 padded_grid(const Geom& g) { return dim3((g.n[0] + 2 * G + 63) / 64, (g.n[1] + 2 * G + 3) / 4, g.n[2] + 2 * G); }
@@ -1008,6 +1022,65 @@ int dcopy(igr_ctx* c, double* dst, const double* src, int nf, hipStream_t s) {
 
 int dzero(igr_ctx* c, double* p, int nf, hipStream_t s) {
     IGR_HIP(hipMemsetAsync(p, 0, (size_t)nf * field_bytes(c, sizeof(double)), s));
+    return IGR_OK;
+}
+
+// Viscous part of a right-hand side's adjoint: adds into Ubpad (padded
+// state cotangent) what L_v(U) contributes for the cotangent Lb.  U's
+// ghosts are filled; the stress of U is formed again into d_G.
+int viscous_adjoint(igr_ctx* c, const double* U, const double* Lb, double* Ubpad, hipStream_t s) {
+    using F = Plain<double>;
+    const Geom& g = c->g;
+    double* T6 = static_cast<double*>(c->d_G);
+    double* FV = vbuf(c, V_FV);
+    double* Tb = vbuf(c, V_TB);
+    double* Tf = vbuf(c, V_TF);
+    double* Gb = vbuf(c, V_GB);
+    const double* Z = vbuf(c, V_ZERO);
+    const FluxLaunch LS = flux_launch(g, IGR_STRESS_TY, IGR_STRESS_BLOCKS);
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+        k_stress<F, IGR_STRESS_TY, false><<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
+            U, nullptr, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
+    }));
+    for (int q = 0; q < 6; ++q) IGR_TRY(fill_sigma_ghosts(c, T6 + (size_t)q * g.fs, s));
+    IGR_TRY(dzero(c, Tb, 6, s));
+    for (int d = 0; d < 3; ++d) {
+        const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        const long long lines = (long long)g.n[a] * g.n[b];
+        const int bf = int((lines * (g.n[d] + 1) + 255) / 256);
+        const int bg = int((lines * (g.n[d] + 2 * G) + 255) / 256);
+        auto faces = [&](auto dd, auto order) {
+            constexpr int DD = decltype(dd)::value, OR = decltype(order)::value;
+            k_adj_visc_face<DD, OR><<<bf, 256, 0, s>>>(U, T6, Lb, FV, g);
+            k_adj_visc_gather<DD, OR><<<bg, 256, 0, s>>>(FV, Ubpad, Tb, g);
+        };
+        IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+            using O3 = std::integral_constant<int, 3>;
+            using O5 = std::integral_constant<int, 5>;
+            if (d == 0) {
+                if (c->order == 3) faces(std::integral_constant<int, 0>{}, O3{});
+                else faces(std::integral_constant<int, 0>{}, O5{});
+            } else if (d == 1) {
+                if (c->order == 3) faces(std::integral_constant<int, 1>{}, O3{});
+                else faces(std::integral_constant<int, 1>{}, O5{});
+            } else {
+                if (c->order == 3) faces(std::integral_constant<int, 2>{}, O3{});
+                else faces(std::integral_constant<int, 2>{}, O5{});
+            }
+        }));
+    }
+    // tau's ghost copies folded back (the rule is Sigma's), then tau(G) and
+    // the central differences of u
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+        for (int q = 0; q < 6; ++q)
+            k_adj_sigma_bc<<<cell_grid(g), cell_block(), 0, s>>>(Tb + (size_t)q * g.fs, Z, Tf + (size_t)q * g.fs, g);
+    }));
+    IGR_TRY(dzero(c, Gb, 9, s));
+    const dim3 ugrid(unsigned((g.n[0] + 2 + 63) / 64), unsigned((g.n[1] + 2 + 3) / 4), unsigned(g.n[2] + 2));
+    IGR_TRY(launch(c, K_ADJOINT, s, [&] {
+        k_adj_stress_g<<<cell_grid(g), cell_block(), 0, s>>>(Tf, Gb, g, c->mu, c->zeta);
+        k_adj_stress_u<<<ugrid, cell_block(), 0, s>>>(U, Gb, Ubpad, g);
+    }));
     return IGR_OK;
 }
 
@@ -1071,6 +1144,7 @@ int stage_adjoint(igr_ctx* c, double* U, const double* Sp, const double* Lb, con
             }
         }));
     }
+    if (c->viscous) IGR_TRY(viscous_adjoint(c, U, Lb, Ubpad, s));
     // Sigma ghosts transposed: sbA = Sigma^S-bar
     IGR_TRY(launch(c, K_ADJOINT, s, [&] { k_adj_sigma_bc<<<cell_grid(g), cell_block(), 0, s>>>(Sbpad, Sbn, sbA, g); }));
     // Jacobi levels in reverse
@@ -1508,7 +1582,6 @@ int igr_rhs_adjoint(igr_ctx* ctx, void* U, const void* sigma_prev, const void* r
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
-    if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
     // inputs may alias outputs: stage them
@@ -1534,7 +1607,6 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
         return fail(IGR_EINVAL, "null argument");
     if (ctx->precision != IGR_F64) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for IGR_F64");
     if (ctx->smoother != IGR_SMOOTH_JACOBI) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for Jacobi sweeps");
-    if (ctx->viscous) return fail(IGR_EUNSUPPORTED, "the adjoint is implemented for the Euler system (no viscosity)");
     if (!(dt > 0.0)) return fail(IGR_EINVAL, "the step adjoint needs a fixed dt > 0");
     hipStream_t s = as_stream(stream);
     IGR_TRY(adjoint_buffers(ctx));
@@ -1553,10 +1625,12 @@ int igr_step_adjoint(igr_ctx* ctx, void* U_n, const void* sigma_n, double dt, co
     IGR_TRY(dcopy(ctx, sig1, (const double*)sigma_n, 1, s));
     IGR_TRY(sigma_solve_impl<Plain<double>>(ctx, Un, sig1, S, s));
     IGR_TRY((flux_impl<Plain<double>, MODE_STAGE1>(ctx, Un, nullptr, sig1, nullptr, U1, nullptr, dt, s)));
+    if (ctx->viscous) IGR_TRY((viscous_impl<Plain<double>, MODE_STAGE1>(ctx, Un, nullptr, U1, nullptr, dt, s)));
     IGR_TRY(fill_state_ghosts(ctx, U1, s));
     IGR_TRY(dcopy(ctx, sig2, sig1, 1, s));
     IGR_TRY(sigma_solve_impl<Plain<double>>(ctx, U1, sig2, S, s));
     IGR_TRY((flux_impl<Plain<double>, MODE_STAGE2>(ctx, U1, nullptr, sig2, Un, U2, nullptr, dt, s)));
+    if (ctx->viscous) IGR_TRY((viscous_impl<Plain<double>, MODE_STAGE2>(ctx, U1, nullptr, U2, nullptr, dt, s)));
     // reverse sweep over the stages
     double* Ubn = abuf(ctx, A_UBN);
     double* Ub1 = abuf(ctx, A_UB1);

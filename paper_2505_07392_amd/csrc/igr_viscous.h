@@ -37,6 +37,7 @@
 // from global memory would fetch each z stencil seven times.
 #pragma once
 
+#include "igr_adjoint.h"
 #include "igr_flux.h"
 
 namespace igr {
@@ -546,6 +547,185 @@ __global__ __launch_bounds__(VISC_TX*(TY + 1), MINW) void k_viscous_tiled(const 
         }
         if (bad) flag[0] = 1;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the viscous terms (FP64; the right-hand side's part
+// L_v(U) = -sum_d (F(+1/2) - F(-1/2)) / h_d of the momenta and energy).
+// Reverse order: face fluxes -> reconstructed sides -> cell values of
+// rho, m (into the state's cotangent) and of tau (into Tb, 6 components,
+// ghost positions included) -> tau's ghost copies folded back -> tau(G)
+// -> G by central differences of u = m / rho -> rho, m.
+// ---------------------------------------------------------------------------
+
+// Per face l+1/2 (l = -1..n-1) of direction D: the cotangents of the two
+// sides' reconstructed rho, m, tau_xD, tau_yD, tau_zD, stored at padded
+// position l+1 along D: FV[0..6] left, FV[7..13] right.
+template <int D, int ORDER>
+__global__ __launch_bounds__(256) void k_adj_visc_face(const double* __restrict__ U, const double* __restrict__ T6,
+                                                       const double* __restrict__ Lb, double* __restrict__ FV,
+                                                       Geom g) {
+    const Line tl = transverse(D);
+    const int nd = g.n[D];
+    const long long nlines = (long long)g.n[tl.a] * g.n[tl.b];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlines * (nd + 1)) return;
+    const int f = int(t % (nd + 1));
+    const long long line = t / (nd + 1);
+    const int ia = int(line % g.n[tl.a]);
+    const int ib = int(line / g.n[tl.a]);
+    const int sd = g.st[D];
+    const long long base = (long long)(ia + G) * g.st[tl.a] + (long long)(ib + G) * g.st[tl.b];
+    const int l = f - 1;
+    const long long ol = base + (long long)(l + G) * sd;   // left cell of the face
+    // face flux cotangents (momenta, energy) from the two cells' L-bar
+    double Fb[4];
+    for (int c = 0; c < 4; ++c) {
+        const double right = (l + 1 <= nd - 1) ? Lb[(1 + c) * g.fs + ol + sd] : 0.0;
+        const double left = (l >= 0) ? Lb[(1 + c) * g.fs + ol] : 0.0;
+        Fb[c] = (right - left) * g.ih[D];
+    }
+    // forward: the sides of rho, m, tau_cD from cells l-2..l+3
+    double q[7][6];
+    for (int p = 0; p < 6; ++p) {
+        const long long op = ol + (long long)(p - 2) * sd;
+        for (int k = 0; k < 4; ++k) q[k][p] = U[k * g.fs + op];
+        for (int c = 0; c < 3; ++c) q[4 + c][p] = T6[(long long)tau_index(c, D) * g.fs + op];
+    }
+    double rl[7], rr[7];
+    for (int k = 0; k < 7; ++k) {
+        if constexpr (ORDER == 5) {
+            rl[k] = recon_left(q[k][0], q[k][1], q[k][2], q[k][3], q[k][4]);
+            rr[k] = recon_right(q[k][1], q[k][2], q[k][3], q[k][4], q[k][5]);
+        } else {
+            rl[k] = recon3_left(q[k][1], q[k][2], q[k][3]);
+            rr[k] = recon3_right(q[k][2], q[k][3], q[k][4]);
+        }
+    }
+    const double il = 1.0 / rl[0], ir = 1.0 / rr[0];
+    // reverse of F_c = -1/2 (tl_c + tr_c), F_E = -1/2 sum_c (ml_c il tl_c + mr_c ir tr_c)
+    double lb[7] = {0, 0, 0, 0, 0, 0, 0}, rb[7] = {0, 0, 0, 0, 0, 0, 0};
+    const double eb = -0.5 * Fb[3];
+    double ilb = 0.0, irb = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        lb[4 + c] += -0.5 * Fb[c] + eb * rl[1 + c] * il;
+        rb[4 + c] += -0.5 * Fb[c] + eb * rr[1 + c] * ir;
+        lb[1 + c] += eb * il * rl[4 + c];
+        rb[1 + c] += eb * ir * rr[4 + c];
+        ilb += eb * rl[1 + c] * rl[4 + c];
+        irb += eb * rr[1 + c] * rr[4 + c];
+    }
+    lb[0] -= ilb * il * il;
+    rb[0] -= irb * ir * ir;
+    const long long of = base + (long long)(f + G) * sd;
+    for (int k = 0; k < 7; ++k) {
+        FV[k * g.fs + of] = lb[k];
+        FV[(7 + k) * g.fs + of] = rb[k];
+    }
+}
+
+// Transposed reconstruction of the viscous sides: padded cell q along D
+// (q = -3..n+2) gathers from the faces whose stencils contain it; rho, m
+// add into Ub (the state's padded cotangent), tau_cD into Tb.
+template <int D, int ORDER>
+__global__ __launch_bounds__(256) void k_adj_visc_gather(const double* __restrict__ FV, double* __restrict__ Ub,
+                                                         double* __restrict__ Tb, Geom g) {
+    const Line tl = transverse(D);
+    const int nd = g.n[D];
+    const int np = nd + 2 * G;
+    const long long nlines = (long long)g.n[tl.a] * g.n[tl.b];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlines * np) return;
+    const int qp = int(t % np) - G;
+    const long long line = t / np;
+    const int ia = int(line % g.n[tl.a]);
+    const int ib = int(line / g.n[tl.a]);
+    const int sd = g.st[D];
+    const long long base = (long long)(ia + G) * g.st[tl.a] + (long long)(ib + G) * g.st[tl.b];
+    constexpr int NS = ORDER == 5 ? 5 : 3;
+    constexpr int SL = ORDER == 5 ? 2 : 1;
+    constexpr int SR = ORDER == 5 ? 1 : 0;
+    constexpr double DEN = ORDER == 5 ? 60.0 : 6.0;
+    const double CLc[5] = {ORDER == 5 ? 2.0 : -1.0, ORDER == 5 ? -13.0 : 5.0, ORDER == 5 ? 47.0 : 2.0, 27.0, -3.0};
+    const double CRc[5] = {ORDER == 5 ? -3.0 : 2.0, ORDER == 5 ? 27.0 : 5.0, ORDER == 5 ? 47.0 : -1.0, -13.0, 2.0};
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int m = 0; m < NS; ++m) {
+        const int lL = qp + SL - m;
+        if (lL >= -1 && lL <= nd - 1) {
+            const long long of = base + (long long)(lL + 1 + G) * sd;
+            const double w = CLc[m] / DEN;
+            for (int k = 0; k < 7; ++k) acc[k] += w * FV[k * g.fs + of];
+        }
+        const int lR = qp + SR - m;
+        if (lR >= -1 && lR <= nd - 1) {
+            const long long of = base + (long long)(lR + 1 + G) * sd;
+            const double w = CRc[m] / DEN;
+            for (int k = 0; k < 7; ++k) acc[k] += w * FV[(7 + k) * g.fs + of];
+        }
+    }
+    const long long oc = base + (long long)(qp + G) * sd;
+    for (int k = 0; k < 4; ++k) Ub[k * g.fs + oc] += acc[k];
+    for (int c = 0; c < 3; ++c) Tb[(long long)tau_index(c, D) * g.fs + oc] += acc[4 + c];
+}
+
+// tau's cotangent at interior cells (ghost copies folded back, Tf) ->
+// the cotangent of G: Gb_ab = mu Tf[ab] for a != b, and
+// 2 mu Tf[aa] + lambda sum_c Tf[cc] on the diagonal; written at interior
+// cells of Gb (9 fields, row-major a, b; ghosts stay zero).
+__global__ __launch_bounds__(256) void k_adj_stress_g(const double* __restrict__ Tf, double* __restrict__ Gb, Geom g,
+                                                      double mu, double zeta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long long o = cell_offset(g, i, j, k);
+    const double lam = zeta - 2.0 * mu / 3.0;
+    const double trb = Tf[(long long)tau_index(0, 0) * g.fs + o] + Tf[(long long)tau_index(1, 1) * g.fs + o] +
+                       Tf[(long long)tau_index(2, 2) * g.fs + o];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double tb = Tf[(long long)tau_index(a, b) * g.fs + o];
+            Gb[(long long)(3 * a + b) * g.fs + o] = a == b ? 2.0 * mu * tb + lam * trb : mu * tb;
+        }
+}
+
+// G_ab = (u_a(x + e_b) - u_a(x - e_b)) / (2 h_b), u = m / rho: every padded
+// cell within one layer of the interior gathers u-bar from the interior
+// cells that difference it, then adds rho-bar and m-bar into Ub.
+__global__ __launch_bounds__(256) void k_adj_stress_u(const double* __restrict__ U, const double* __restrict__ Gb,
+                                                      double* __restrict__ Ub, Geom g) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - 1;
+    const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - 1;
+    const int k = int(blockIdx.z) - 1;
+    if (i > g.n[0] || j > g.n[1] || k > g.n[2]) return;
+    const int idx[3] = {i, j, k};
+    // a cell outside the interior in two axes (an edge or corner of the
+    // ghost layer, never filled) is differenced by no interior cell
+    int outside = 0;
+    for (int d = 0; d < 3; ++d) outside += (idx[d] < 0 || idx[d] >= g.n[d]) ? 1 : 0;
+    if (outside > 1) return;
+    const long long o = cell_offset(g, i, j, k);
+    double ub[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < 3; ++b) {
+        const double sc = 0.5 * g.ih[b];
+        // the interior neighbours x = q - e_b (which reads q as its + side)
+        // and x = q + e_b (which reads q as its - side)
+        const bool hm = idx[b] - 1 >= 0 && idx[b] - 1 < g.n[b];
+        const bool hp = idx[b] + 1 >= 0 && idx[b] + 1 < g.n[b];
+        for (int a = 0; a < 3; ++a) {
+            const double* Ga = Gb + (long long)(3 * a + b) * g.fs;
+            if (hm) ub[a] += sc * Ga[o - g.st[b]];
+            if (hp) ub[a] -= sc * Ga[o + g.st[b]];
+        }
+    }
+    const double rho = U[o];
+    const double r = 1.0 / rho;
+    double rb = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        Ub[(long long)(1 + a) * g.fs + o] += ub[a] * r;
+        rb -= ub[a] * U[(long long)(1 + a) * g.fs + o] * r * r;
+    }
+    Ub[o] += rb;
 }
 
 }  // namespace igr

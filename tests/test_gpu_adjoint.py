@@ -2,8 +2,8 @@
 
 * igr_rhs_adjoint and igr_step_adjoint against the oracle's discrete
   adjoint (torch.autograd through oracle/igr_ref.py) on the same inputs,
-  with fifth- and third-order reconstruction: cotangents of U, of the
-  warm-start Sigma and of the jet pressures.
+  with fifth- and third-order reconstruction, without and with the viscous
+  terms: cotangents of U, of the warm-start Sigma and of the jet pressures.
 * Transposition: <J v, w> computed by central differences of the GPU
   forward equals <v, J^T w> from the adjoint.
 * The 128^3 gradient workload (2 x 2 Mach-2 jets, 40 fixed-dt steps,
@@ -66,11 +66,23 @@ CASES = {
 }
 
 
+# shear and bulk viscosity of the viscous cases (eq. (5))
+VISC = (2e-3, 1e-3)
+
+
+def _with_viscosity(w, visc):
+    if visc:
+        w = w.with_state(w.U)
+        w.mu, w.zeta = VISC
+    return w
+
+
+@pytest.mark.parametrize("visc", [False, True])
 @pytest.mark.parametrize("order", [5, 3])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_rhs_adjoint_matches_oracle_autograd(name, order):
-    w = CASES[name]()
-    banner(f"rhs adjoint {name} order {order}")
+def test_rhs_adjoint_matches_oracle_autograd(name, order, visc):
+    w = _with_viscosity(CASES[name](), visc)
+    banner(f"rhs adjoint {name} order {order} viscous {visc}")
     rng = np.random.default_rng(5)
     sig0 = rng.random((w.nz, w.ny, w.nx)) * 0.1
     Lbar = rng.standard_normal((5, w.nz, w.ny, w.nx))
@@ -91,12 +103,21 @@ def test_rhs_adjoint_matches_oracle_autograd(name, order):
     assert _rel(to_host(s, Sb), grads[1].numpy()) <= ADJ_TOL
     if w.jets:
         assert abs(pb[0, 4].item() - grads[2][0].item()) <= ADJ_TOL * abs(grads[2][0].item())
+    if visc:
+        # the viscous terms move the gradient far beyond the tolerance
+        w0 = w.with_state(w.U)
+        w0.mu, w0.zeta = 0.0, 0.0
+        U0 = torch.from_numpy(w.U.copy()).requires_grad_(True)
+        L0, S0n = ref.rhs(_oracle_problem(w0, None, order), U0, torch.from_numpy(sig0))
+        g0 = torch.autograd.grad((L0, S0n), (U0,), (torch.from_numpy(Lbar), torch.from_numpy(Sbar)))[0]
+        assert _rel(g0.numpy(), grads[0].numpy()) > 1e3 * ADJ_TOL
 
 
+@pytest.mark.parametrize("visc", [False, True])
 @pytest.mark.parametrize("order", [5, 3])
-def test_step_adjoint_matches_oracle_autograd(order):
-    w = _case(16, 8, 6, seed=3)
-    banner(f"step adjoint vs oracle autograd, order {order}")
+def test_step_adjoint_matches_oracle_autograd(order, visc):
+    w = _with_viscosity(_case(16, 8, 6, seed=3), visc)
+    banner(f"step adjoint vs oracle autograd, order {order}, viscous {visc}")
     rng = np.random.default_rng(6)
     sig0 = rng.random((w.nz, w.ny, w.nx)) * 0.1
     Ubar = rng.standard_normal((5, w.nz, w.ny, w.nx))

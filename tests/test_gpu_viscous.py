@@ -4,8 +4,7 @@ RK3 steps with shear and bulk viscosity on the mixed small cases (jet discs,
 periodic and outflow faces, ragged tiles), third-order reconstruction, the
 viscous contribution on its own (L(mu, zeta) - L(0, 0), at 1e-10 of its own
 size), conservation on a periodic box, the FP32, 16-bit storage and split forms,
-the 256^3 box on sampled windows, and the entry points that reject
-viscosity."""
+the 256^3 box on sampled windows, and the adjoint's FP64-only rule."""
 
 import numpy as np
 import pytest
@@ -224,11 +223,13 @@ def test_viscous_full_size_step_sampled():
         assert abs(Sg[k, j, i] - float(Sw[R, R, R])) <= TOL * np.abs(Sg).max()
 
 
-def test_viscous_rejections():
-    """The adjoint is of the Euler system: it rejects viscous contexts."""
+def test_viscous_adjoint_runs_in_fp64_only():
+    """The adjoint (checked against the oracle's autograd with viscosity in
+    tests/test_gpu_adjoint.py) is an FP64 feature: an FP32 viscous context
+    reports IGR_EUNSUPPORTED."""
     w = _viscous(CASES["mixed_70x9x7"]())
-    banner("viscous rejections")
-    s = igr.Solver.from_workload(w)
+    banner("viscous adjoint: FP32 rejected")
+    s = igr.Solver.from_workload(w, precision="f32")
     U = s.state_from(w.U)
     sig = s.new_field()
     with pytest.raises(igr.IGRError) as e:
