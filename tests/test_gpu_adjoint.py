@@ -5,11 +5,13 @@
   with fifth- and third-order reconstruction, without and with the viscous
   terms: cotangents of U, of the warm-start Sigma and of the jet pressures.
 * Transposition: <J v, w> computed by central differences of the GPU
-  forward equals <v, J^T w> from the adjoint.
+  forward equals <v, J^T w> from the adjoint, without and with the viscous
+  terms.
 * The 128^3 gradient workload (2 x 2 Mach-2 jets, 40 fixed-dt steps,
   checkpoints every 10 steps, loss = time-integrated thermodynamic pressure
   force on the plane x = 0.75 L): dJ/dp_jet and a random-direction dJ/drho0
-  against central finite differences (h = 1e-6), <= 1e-6 relative.
+  against central finite differences (h = 1e-6), <= 1e-6 relative; the
+  same at x = 4 dx with the viscous terms.
 """
 
 import math
@@ -136,10 +138,11 @@ def test_step_adjoint_matches_oracle_autograd(order, visc):
     assert abs(pb[0, 4].item() - gp[0].item()) <= ADJ_TOL * abs(gp[0].item())
 
 
-def test_step_adjoint_transposition_fd():
+@pytest.mark.parametrize("visc", [False, True])
+def test_step_adjoint_transposition_fd(visc):
     """<(F(U + h v) - F(U - h v)) / 2h, w> = <v, J^T w> on the GPU alone."""
-    w = _case(24, 10, 8, seed=4)
-    banner("step adjoint transposition")
+    w = _with_viscosity(_case(24, 10, 8, seed=4), visc)
+    banner(f"step adjoint transposition (viscous {visc})")
     rng = np.random.default_rng(8)
     dt = 0.3 * ref.compute_dt(problem_from(w), torch.from_numpy(w.U), 0.5)
     v = rng.standard_normal(w.U.shape) * np.abs(w.U).max(axis=(1, 2, 3), keepdims=True) * 1e-2
@@ -175,18 +178,13 @@ def _plane_loss(s, w, dt, i0):
     return loss
 
 
-@pytest.mark.parametrize("plane", ["x=0.75L", "x=4dx"])
-def test_gradient_workload_128_against_finite_differences(plane):
-    """At x = 0.75 L (the specified plane) no signal from the inlet arrives
-    within 40 steps (at most ~0.3 cells per step), and with u = 0 there a
-    density perturbation leaves p unchanged, so dJ/dp_jet and dJ/drho0 are
-    zero in exact arithmetic: the finite differences give exactly 0 and the
-    adjoint gives round-off.  The plane at 4 cells lies in the jets' initial
-    plug, where the derivatives are far above the h = 1e-6 noise floor
-    (about 1e-16 J / h), and adjoint and central differences must agree to
-    1e-6 relative."""
-    w = inputs.gradient_jets(128)
-    banner(f"gradient workload 128^3: 40 steps, checkpoints every 10, FD h=1e-6, plane {plane}")
+# viscosity of the viscous gradient case: cell Reynolds number about 40 in
+# the jets, viscous diffusion number about 5e-3 at the workload's fixed dt
+GRAD_VISC = (1e-3, 5e-4)
+
+
+def _gradient_run(w, plane):
+    """Adjoint gradients (dJ/dp_jet, dJ/dU0) and J of the 128^3 workload."""
     s = igr.Solver.from_workload(w)
     dt = w.dt_fixed
     i0 = int(0.75 * w.nx) if plane == "x=0.75L" else 4
@@ -196,9 +194,36 @@ def test_gradient_workload_128_against_finite_differences(plane):
     p = torch.tensor([j.p for j in w.jets], dtype=torch.float64, requires_grad=True)
     J, _, _ = run_checkpointed(s, U0, S0, p, dt, w.nsteps, loss_fn, every=10)
     J.backward()
-    Jv = float(J)
-    gp = p.grad.clone()
-    gU = U0.grad.detach().clone()
+    return s, loss_fn, float(J), p.grad.clone(), U0.grad.detach().clone()
+
+
+@pytest.mark.parametrize("plane", ["x=0.75L", "x=4dx", "x=4dx viscous"])
+def test_gradient_workload_128_against_finite_differences(plane):
+    """At x = 0.75 L (the specified plane) no signal from the inlet arrives
+    within 40 steps (at most ~0.3 cells per step), and with u = 0 there a
+    density perturbation leaves p unchanged, so dJ/dp_jet and dJ/drho0 are
+    zero in exact arithmetic: the finite differences give exactly 0 and the
+    adjoint gives round-off.  The plane at 4 cells lies in the jets' initial
+    plug, where the derivatives are far above the h = 1e-6 noise floor
+    (about 1e-16 J / h), and adjoint and central differences must agree to
+    1e-6 relative.  The viscous case runs the same workload with the
+    viscous terms of eq. (5), which must move dJ/dp_jet by far more than
+    that tolerance."""
+    w = inputs.gradient_jets(128)
+    visc = plane.endswith("viscous")
+    plane = plane.split()[0]
+    if visc:
+        w0 = w
+        w = w.with_state(w.U)
+        w.mu, w.zeta = GRAD_VISC
+    banner(f"gradient workload 128^3: 40 steps, checkpoints every 10, FD h=1e-6, plane {plane}, viscous {visc}")
+    s, loss_fn, Jv, gp, gU = _gradient_run(w, plane)
+    dt = w.dt_fixed
+    if visc:
+        gp0 = _gradient_run(w0, plane)[3]
+        moved = float((gp - gp0).abs().max() / gp.abs().max())
+        print(f"[gpu-case] viscous terms move dJ/dp_jet by {moved:.3e} (relative)", flush=True)
+        assert moved > 1e-4
 
     def J_of(pv, Uv):
         with torch.no_grad():
