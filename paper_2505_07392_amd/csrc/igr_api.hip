@@ -289,8 +289,9 @@ PairShape pair_shape(const Geom& g, int nr) {
 long long pair_speed_slots(const Geom& g) { return pair_shape(g, PAIR_NR_FIRST).blocks * (PAIR_NR_FIRST + 1); }
 
 // speed (FIRST, FP64 state without a difference; nullable): the pass also
-// leaves the CFL maxima of U there.
-template <class F, bool FIRST, bool HASD>
+// leaves the CFL maxima of U there.  RB: one red-black sweep per pass
+// instead of two Jacobi sweeps.
+template <class F, bool FIRST, bool HASD, bool RB = false>
 int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* Sin,
               typename F::TS* Sout, hipStream_t s, double* speed = nullptr) {
     using C = typename F::C;
@@ -307,11 +308,11 @@ int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, cons
     return launch(c, K_JACOBI, s, [&] {
         if (spd) {
             if constexpr (SPD_OK)
-                k_sweep_pair<F, PAIR_NR_FIRST, true, false, true>
+                k_sweep_pair<F, PAIR_NR_FIRST, true, false, true, RB>
                     <<<dim3(unsigned(sh.blocks)), dim3(64, PAIR_NR_FIRST + 1), 0, s>>>(
                         U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
         } else {
-            k_sweep_pair<F, NR, FIRST, HASD><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
+            k_sweep_pair<F, NR, FIRST, HASD, false, RB><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
                 U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y);
         }
     });
@@ -399,8 +400,25 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
                 }
             });
         };
+        if (c->smoother == IGR_SMOOTH_RBGS && c->sigma_block == 2) {
+            // red-black Gauss-Seidel, one pass per sweep (both halves; the
+            // first pass also forms b and, FP64, the CFL maxima of U)
+            for (int it = 0; it < nsweeps; ++it) {
+                if (it == 0) {
+                    const bool spd = sizeof(C) == 8 && !HASD && speed != nullptr;
+                    IGR_TRY((pair_pass<F, true, HASD, true>(c, U, D, src, dst, s, spd ? speed : nullptr)));
+                    if (spd && nspeed) *nspeed = int(pair_speed_slots(c->g));
+                } else {
+                    IGR_TRY((pair_pass<F, false, HASD, true>(c, U, D, src, dst, s)));
+                }
+                swap();
+            }
+            *result = src;
+            return fill_sigma_ghosts(c, src, s);
+        }
         if (c->smoother == IGR_SMOOTH_RBGS) {
-            // red-black Gauss-Seidel: red half (the first also forms b), then black
+            // red-black Gauss-Seidel in place, a launch per half-sweep: red
+            // (the first also forms b), then black
             for (int it = 0; it < nsweeps; ++it) {
                 IGR_TRY(single(it == 0, 0));
                 IGR_TRY(single(false, 1));

@@ -648,10 +648,18 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
 // non-physical states raise *flag.
 // F: storage form; the state swept from is U (+ D with HASD, the split
 // form's stage difference).
+// RB: one red-black Gauss-Seidel sweep instead of two Jacobi sweeps:
+// level 1 applies the update to the red cells ((i + j + k) even) and keeps
+// the black ones, level 2 applies it to the black cells from level 1's
+// values and keeps the red ones.  Every neighbour of a cell has the other
+// colour, so level 1 is the red half-sweep from the values at its start
+// and level 2 the black half-sweep (a zero-gradient face reads the cell's
+// own value at the start of its half: the old value for red, level 1's
+// for black); periodic axes must have even extents.
 #ifndef IGR_SPLIT_FIRST_MINW
 #define IGR_SPLIT_FIRST_MINW 4
 #endif
-template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false>
+template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false, bool RB = false>
 __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SPLIT_FIRST_MINW : 1) void k_sweep_pair(const typename F::TB* __restrict__ U,
                                                             const typename F::TD* __restrict__ D,
                                                             const typename F::TS* __restrict__ Sin,
@@ -714,6 +722,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
         }
     }
     const int gx = x0 + lx, gy = y0 - 1 + ly;
+    const int par = (gx + gy) & 1;   // RB: colour of the own column's cell at z = 0
     const bool outp = threadIdx.y < NR && ly >= 1 && ly <= NR - 2 && gx < nx && gy < ny;
     const bool xrow = threadIdx.y < NR && (ly == 0 || ly == NR - 1);
     const int gyx = xrow ? (ly == 0 ? y0 - 2 : y0 + NR - 1) : gy;
@@ -899,6 +908,7 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                 bn = lb[(r + 2) % 3][ly][bxc];
             }
             v1 = jacobi_apply(bn, kn, sgv, ja);
+            if constexpr (RB) v1 = ((par + z) & 1) ? sc : v1;   // black cells keep their value
             if (lev1) ls1[(r + 1) & 1][ly][bxc] = v1;
         }
         // level 2 (output) at plane P-2, with the coefficients and source
@@ -912,7 +922,8 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                               face_or<NBSEL>(ylo, sc, &ls1[a2][ly - 1][bxc]),
                               face_or<NBSEL>(yhi, sc, &ls1[a2][ly + 1][bxc]),
                               (!pz && z2 == 0) ? sc : qs1[0], (!pz && z2 == nz - 1) ? sc : v1};
-            const C v2 = jacobi_apply(bprev, kc, sgv, ja);
+            C v2 = jacobi_apply(bprev, kc, sgv, ja);
+            if constexpr (RB) v2 = ((par + z2) & 1) ? v2 : sc;   // red cells keep level 1's value
             SS::store(Sout + (long long)(z2 + G) * sz + (long long)(gy + G) * sy + (gx + G), v2);
         }
         kc = kn;

@@ -133,19 +133,22 @@ def _even_periodic(w):
     return all(w.faces[2 * d] != "periodic" or ext[d] % 2 == 0 for d in range(3))
 
 
+@pytest.mark.parametrize("sigma_block", [1, 2])
 @pytest.mark.parametrize("nsweeps", [1, 5])
-def test_sigma_solve_red_black(case, nsweeps):
+def test_sigma_solve_red_black(case, nsweeps, sigma_block):
     """Red-black Gauss-Seidel sweeps (the paper's alternative smoother)
-    against the oracle's red-black ordering; grids with an odd periodic
-    extent are rejected (a cell would neighbour its own colour)."""
+    against the oracle's red-black ordering, as in-place half-sweep launches
+    (sigma_block 1) and as one two-level pass per sweep (2); grids with an
+    odd periodic extent are rejected (a cell would neighbour its own
+    colour)."""
     name, w = case
-    banner(f"sigma_solve rbgs {name} nsweeps={nsweeps}")
+    banner(f"sigma_solve rbgs {name} nsweeps={nsweeps} sigma_block={sigma_block}")
     if not _even_periodic(w):
         with pytest.raises(igr.IGRError) as e:
-            igr.Solver.from_workload(w, smoother="rbgs")
+            igr.Solver.from_workload(w, smoother="rbgs", sigma_block=sigma_block)
         assert e.value.code == igr.IGR_EUNSUPPORTED
         return
-    s = igr.Solver.from_workload(w, smoother="rbgs")
+    s = igr.Solver.from_workload(w, smoother="rbgs", sigma_block=sigma_block)
     U = s.state_from(w.U)
     sig = s.field_from(_sigma0(w))
     res = s.sigma_solve(U, sig, nsweeps=nsweeps, residual=True)
@@ -157,11 +160,12 @@ def test_sigma_solve_red_black(case, nsweeps):
     assert abs(res - want_res) <= 1e-10 * max(want_res, 1e-300)
 
 
-def test_step_red_black():
+@pytest.mark.parametrize("sigma_block", [1, 2])
+def test_step_red_black(sigma_block):
     w = CASES["chunks_130x10x40"]()
     w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 13, amp=0.1, umax=0.3))
-    banner("step x3 rbgs chunks_130x10x40")
-    s = igr.Solver.from_workload(w, smoother="rbgs")
+    banner(f"step x3 rbgs chunks_130x10x40 sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, smoother="rbgs", sigma_block=sigma_block)
     U = s.state_from(w.U)
     sig = s.field_from(_sigma0(w))
     prob = problem_from(w)
@@ -173,6 +177,37 @@ def test_step_red_black():
         Uo, so = ref.rk3_step(prob, Uo, so, dt_o)
     assert rel_linf(to_host(s, U), Uo.numpy()).max() <= TOL
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
+
+
+# per-value bounds of a 5-sweep red-black solve against the FP64 oracle:
+# FP32 arithmetic with FP32 Sigma; the split form stores Sigma in BF16
+RB_FORM_BOUND = {"f32": 1e-5, "bf16d": 1e-2}
+
+
+@pytest.mark.parametrize("sigma_block", [1, 2])
+@pytest.mark.parametrize("precision", ["f32", "bf16d"])
+def test_red_black_forms_against_oracle(precision, sigma_block):
+    """The FP32-arithmetic forms' red-black solve (half-sweep launches, or
+    one pass per sweep) against the oracle's; the oracle's red-black and
+    Jacobi iterates differ by far more than the bound, so a wrong colour
+    order fails."""
+    w = CASES["chunks_130x10x40"]()
+    w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 17, amp=0.1, umax=0.3))
+    banner(f"sigma_solve rbgs {precision} sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, precision=precision, smoother="rbgs", sigma_block=sigma_block)
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    s.sigma_solve(U, sig, nsweeps=5)
+    prob = problem_from(w)
+    prob.smoother = "rbgs"
+    want, _ = ref.sigma_solve(prob, torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)), nsweeps=5)
+    prob.smoother = "jacobi"
+    jac, _ = ref.sigma_solve(prob, torch.from_numpy(w.U), torch.from_numpy(_sigma0(w)), nsweeps=5)
+    err = rel_linf(to_host(s, sig).astype(np.float64), want.numpy()).max()
+    sep = rel_linf(jac.numpy(), want.numpy()).max()
+    print(f"  rel Linf vs oracle {err:.3e}; oracle red-black vs Jacobi {sep:.3e}", flush=True)
+    assert err <= RB_FORM_BOUND[precision]
+    assert sep > 5 * RB_FORM_BOUND[precision]
 
 
 def test_red_black_residual_below_jacobi():
@@ -251,15 +286,16 @@ def test_advance_equals_repeated_steps(case, precision):
     assert rel_linf(to_host(s, S2).astype(np.float64), to_host(s, S1).astype(np.float64)).max() <= tol
 
 
-@pytest.mark.parametrize("nsweeps,smoother", [(5, "jacobi"), (4, "jacobi"), (10, "jacobi"), (1, "jacobi"),
-                                              (3, "rbgs")])
-def test_cfl_dt_of_a_step_equals_the_standalone_reduction(nsweeps, smoother):
+@pytest.mark.parametrize("nsweeps,smoother,sigma_block", [(5, "jacobi", 0), (4, "jacobi", 0), (10, "jacobi", 0),
+                                                          (1, "jacobi", 0), (3, "rbgs", 2), (3, "rbgs", 1)])
+def test_cfl_dt_of_a_step_equals_the_standalone_reduction(nsweeps, smoother, sigma_block):
     """FP64 steps form the CFL maxima in the first pass of the first Sigma
-    solve: a single first sweep (odd counts, red-black) or a first two-sweep
-    pass (even counts): the time step is bitwise the standalone one."""
+    solve: a single first sweep (odd counts, red-black half-sweeps) or a
+    first two-level pass (even counts, red-black passes): the time step is
+    bitwise the standalone one."""
     w = _mixed_workload(20, 40, 10, 6, faces=("extrap", "extrap", "periodic", "periodic", "periodic", "periodic"))
-    banner(f"cfl dt fused vs standalone nsweeps={nsweeps} {smoother}")
-    s = igr.Solver.from_workload(w, nsweeps=nsweeps, smoother=smoother)
+    banner(f"cfl dt fused vs standalone nsweeps={nsweeps} {smoother} sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, nsweeps=nsweeps, smoother=smoother, sigma_block=sigma_block)
     U = s.state_from(w.U)
     S = s.field_from(_sigma0(w))
     for _ in range(2):
