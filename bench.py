@@ -43,12 +43,13 @@ def sigma_schedule(nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
     (passes that form the source, later two-sweep passes, later single
     sweeps).  With two-sweep passes an even count starts with a two-sweep
     pass that forms the source, an odd count with a single sweep.
-    Red-black Gauss-Seidel runs two in-place half-sweeps per sweep, each
-    counted here as a single sweep."""
+    Red-black Gauss-Seidel runs one two-level pass per sweep with
+    sigma_block 2 (each counted here as a two-sweep pass), else two in-place
+    half-sweeps per sweep, each counted as a single sweep."""
     if nsweeps == 0:
         return 0, 0, 0
     if smoother == "rbgs":
-        return 1, 0, 2 * nsweeps - 1
+        return (1, nsweeps - 1, 0) if sigma_block == 2 else (1, 0, 2 * nsweeps - 1)
     if sigma_block not in (1, 2):
         raise ValueError("the fused-source march passes are not modelled here")
     if sigma_block == 2 and nsweeps % 2 == 0:

@@ -128,9 +128,10 @@ typedef struct {
  * else 2 (igr_get_opts reports the choice).  Results agree to rounding.  smoother selects the
  * sweep: IGR_SMOOTH_JACOBI (default), or IGR_SMOOTH_RBGS, red-black
  * Gauss-Seidel (the paper's alternative, "Discretization"): each sweep
- * updates the cells with i + j + k even, then the others, in place, each
- * colour from the values at the start of its half-sweep (sigma_block is
- * then ignored; periodic axes need even extents, else IGR_EUNSUPPORTED;
+ * updates the cells with i + j + k even, then the others, each colour from
+ * the values at the start of its half-sweep (with sigma_block 2 one pass
+ * per sweep forms both halves; otherwise each half is a launch of its own,
+ * in place; periodic axes need even extents, else IGR_EUNSUPPORTED;
  * the adjoint entry points need Jacobi). */
 typedef struct {
     int32_t precision;

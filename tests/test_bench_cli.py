@@ -44,6 +44,23 @@ def test_byte_model():
         bench.algorithmic_bytes_per_cell("nonesuch", "f64", 10)
 
 
+def test_sigma_schedule_counts_the_launches_of_a_solve():
+    """(source-forming passes, later two-sweep passes, later single sweeps)
+    per solve, as the library launches them: an even Jacobi count with
+    two-sweep passes starts with a two-sweep first pass, an odd one with a
+    single first sweep; red-black runs one pass per sweep with two-level
+    passes, else two half-sweep launches per sweep."""
+    assert bench.sigma_schedule(10, 2) == (1, 4, 0)
+    assert bench.sigma_schedule(5, 2) == (1, 2, 0)
+    assert bench.sigma_schedule(5, 1) == (1, 0, 4)
+    assert bench.sigma_schedule(0, 2) == (0, 0, 0)
+    assert bench.sigma_schedule(10, 2, "rbgs") == (1, 9, 0)
+    assert bench.sigma_schedule(10, 1, "rbgs") == (1, 0, 19)
+    # FP64 Jacobi bytes per launch at S = 10: (56 + 4 x 32) / 5 per cell
+    assert bench.algorithmic_bytes_per_cell("jacobi", "f64", 10, 2) == (56 + 4 * 32) / 5
+    assert bench.algorithmic_bytes_per_cell("jacobi", "f64", 10, 2, "rbgs") == (56 + 9 * 32) / 10
+
+
 def test_rooflines_skip_kernels_that_did_not_run():
     kt = {"flux_rk": (84.0, 2), "jacobi": (0.0, 0), "stress": (0.0, 0), "viscous": (0.0, 0)}
     r = bench.kernel_rooflines(kt, 1000, "f64", 10, 2)
