@@ -21,6 +21,12 @@ sample sees the same inputs as on the whole box.  Window inputs come from
 the input definition (`inputs.multi_jet_state_at`), the time step from the
 jet and ambient states.  Tolerance: 1e-12 of each field's maximum (the
 largest |value| of the field over the oracle's windows).
+
+At 512^3 also with red-black Gauss-Seidel sweeps (one two-level pass per
+sweep): a black half-sweep reads red values of the same sweep, so a sweep
+reaches 2 cells and the step 3 (3 + 2 S + 1) = 72; its windows have
+half-width 74, start at even indices (the window's colouring is the box's)
+and wrap with even widths (a periodic axis needs an even extent).
 """
 
 import math
@@ -48,15 +54,19 @@ SAMPLES = {512: [(64, 74, 1), (320, 190, 14), (192, 448, 8), (508, 3, 500)],
            1024: [(128, 138, 1), (640, 382, 14), (384, 896, 8), (1020, 3, 1020)]}
 
 
-# (box size, shear viscosity, bulk viscosity) of each case
-CASES = {"512": (512, 0.0, 0.0), "1024": (1024, 0.0, 0.0), "1024_viscous": (1024, 1e-4, 5e-5)}
+# (box size, shear viscosity, bulk viscosity, smoother) of each case
+CASES = {"512": (512, 0.0, 0.0, "jacobi"), "1024": (1024, 0.0, 0.0, "jacobi"),
+         "1024_viscous": (1024, 1e-4, 5e-5, "jacobi"), "512_rbgs": (512, 0.0, 0.0, "rbgs")}
+# window half-width per smoother (>= the step's dependency radius + B)
+RADIUS = {"jacobi": R, "rbgs": 74}
 
 
-def _workload(n, mu=0.0, zeta=0.0):
+def _workload(n, mu=0.0, zeta=0.0, smoother="jacobi"):
     w = inputs.multi_jet(n=n, jets_per_side=4, radius_cells=10.0, mach=3.0, seed=0, nsweeps=10,
                          build_state=False)
     w.alpha = 4.0 * w.dx * w.dx
     w.mu, w.zeta = mu, zeta
+    w.smoother = smoother
     return w
 
 
@@ -75,22 +85,40 @@ def _block(c, n):
     return np.arange(max(0, c - B), min(n - 1, c + B) + 1)
 
 
-def _axis_window(c, n):
+def _axis_window(c, n, smoother="jacobi"):
     """Index range of the window along one axis and whether it keeps the
-    box's faces (else it wraps)."""
-    if c - R < 0 or c + R > n - 1:
-        lo, hi = max(0, c - R), min(n - 1, c + R)
+    box's faces (else it wraps).  Red-black: the range starts at an even
+    index and a wrapped range has an even width."""
+    r = RADIUS[smoother]
+    rb = smoother == "rbgs"
+    if c - r < 0 or c + r > n - 1:
+        lo, hi = max(0, c - r), min(n - 1, c + r)
+        if rb and lo % 2:
+            lo -= 1
         return np.arange(lo, hi + 1), False
-    return np.arange(c - R, c + R + 1), True
+    lo, hi = c - r, c + r
+    if rb:
+        if lo % 2:
+            lo -= 1
+        else:
+            hi += 1
+        if lo < 0 or hi > n - 1:
+            return _axis_window_faces(c, n, r)
+    return np.arange(lo, hi + 1), True
+
+
+def _axis_window_faces(c, n, r):
+    lo, hi = max(0, c - r - 1), min(n - 1, c + r + 1)
+    return np.arange(lo - lo % 2, hi + 1), False
 
 
 @pytest.fixture(scope="module", params=sorted(CASES))
 def gpu_step(request):
-    N, mu, zeta = CASES[request.param]
-    w = _workload(N, mu, zeta)
+    N, mu, zeta, smoother = CASES[request.param]
+    w = _workload(N, mu, zeta, smoother)
     dt = _dt(w)
-    banner(f"multi-jet {N}^3 FP64 (mu {mu:g}, zeta {zeta:g}): filling the state")
-    s = igr.Solver.from_workload(w, precision="f64")
+    banner(f"multi-jet {N}^3 FP64 (mu {mu:g}, zeta {zeta:g}, {smoother}): filling the state")
+    s = igr.Solver.from_workload(w, precision="f64", smoother=smoother)
     assert s.sigma_block == 2
     U = s.new_state()
     inputs.fill_multi_jet_state(w, s.interior(U))
@@ -123,9 +151,9 @@ def _oracle_window(w, dt, sample):
     of the new state and Sigma, the block's initial state, and the
     window's largest |value| per field."""
     k, j, i = sample
-    ks, kper = _axis_window(k, w.nz)
-    js, jper = _axis_window(j, w.ny)
-    is_, iper = _axis_window(i, w.nx)
+    ks, kper = _axis_window(k, w.nz, w.smoother)
+    js, jper = _axis_window(j, w.ny, w.smoother)
+    is_, iper = _axis_window(i, w.nx, w.smoother)
     U0 = inputs.multi_jet_state_at(w, ks, js, is_)
     faces = []
     for per in (iper, jper, kper):
@@ -137,7 +165,8 @@ def _oracle_window(w, dt, sample):
         patches = tuple(ref.Patch(jt.yc - js[0] * w.dy, jt.zc - ks[0] * w.dz, jt.r, jt.rho, jt.ux, jt.uy, jt.uz,
                                   jt.p, jt.width) for jt in w.jets)
     prob = ref.Problem(len(is_), len(js), len(ks), w.dx, w.dy, w.dz, gamma=w.gamma, alpha=w.alpha,
-                       faces=tuple(faces), patches=patches, nsweeps=w.nsweeps, mu=w.mu, zeta=w.zeta)
+                       faces=tuple(faces), patches=patches, nsweeps=w.nsweeps, mu=w.mu, zeta=w.zeta,
+                       smoother=w.smoother)
     Uo, So = ref.rk3_step(prob, torch.from_numpy(U0), torch.zeros(prob.shape, dtype=torch.float64), dt)
     Uo, So = Uo.numpy(), So.numpy()
     # the compared block in window coordinates
