@@ -210,6 +210,40 @@ def test_red_black_forms_against_oracle(precision, sigma_block):
     assert sep > 5 * RB_FORM_BOUND[precision]
 
 
+@pytest.mark.parametrize("sigma_block", [1, 2])
+@pytest.mark.parametrize("precision", ["f32", "bf16d"])
+def test_step_red_black_forms(precision, sigma_block):
+    """A red-black step with two sweeps per solve (a first and a later
+    pass) in the FP32 and split forms (the split form's later stages sweep
+    from U^n plus the stage difference) against the oracle: the state to
+    the form's step bound, Sigma to the solve bound; the oracle's Jacobi
+    step misses both by far."""
+    w = CASES["chunks_130x10x40"]()
+    w = w.with_state(inputs.random_state(w.nx, w.ny, w.nz, 19, amp=0.1, umax=0.3))
+    banner(f"step rbgs 2 sweeps {precision} sigma_block={sigma_block}")
+    s = igr.Solver.from_workload(w, precision=precision, smoother="rbgs", sigma_block=sigma_block, nsweeps=2)
+    U = s.state_from(w.U)
+    sig = s.field_from(_sigma0(w))
+    prob = problem_from(w, nsweeps=2)
+    dt = ref.compute_dt(prob, torch.from_numpy(w.U), 0.5)
+    out = {}
+    for sm in ("rbgs", "jacobi"):
+        prob.smoother = sm
+        Uo, so = ref.rk3_step(prob, torch.from_numpy(w.U.copy()), torch.from_numpy(_sigma0(w)), dt)
+        out[sm] = (Uo.numpy(), so.numpy())
+    s.step(U, sig, dt_fixed=dt)
+    Uo, so = out["rbgs"]
+    ub = 1e-5 if precision == "f32" else 3e-3
+    eu = rel_linf(to_host(s, U), Uo).max()
+    es = rel_linf(to_host(s, sig), so).max()
+    su = rel_linf(out["jacobi"][0], Uo).max()
+    ss = rel_linf(out["jacobi"][1], so).max()
+    print(f"  rel Linf vs oracle: state {eu:.3e}, Sigma {es:.3e}; oracle red-black vs Jacobi: state {su:.3e}, "
+          f"Sigma {ss:.3e}", flush=True)
+    assert eu <= ub and es <= RB_FORM_BOUND[precision]
+    assert su > 2 * ub and ss > 5 * RB_FORM_BOUND[precision]
+
+
 def test_red_black_residual_below_jacobi():
     """Per sweep, red-black Gauss-Seidel contracts the error faster than
     Jacobi: after 5 sweeps from zero its residual is smaller."""
