@@ -708,17 +708,21 @@ int rhs_impl(igr_ctx* c, typename F::TB* U, typename F::TS* sig, typename F::TB*
 // The new state goes to Unew: the plain forms write it in place (Unew ==
 // U); the split form writes it to the other FP32 state, because its last
 // stage still reads U^n around every cell it writes.
+// Sigma ping-pongs between the caller's buffer `sig` and the scratch copy;
+// the step starts from sig_start (null: sig).  Without sig_end the solved
+// Sigma ends in sig (the last flux stage copies it there when the solve
+// ended in scratch); with sig_end it stays where the solve left it and
+// *sig_end names that buffer (a later step starts from it).
 template <class F>
 int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F::TS* sig, const double* dtp,
-                double dt_fixed, hipStream_t s, double* speed, bool cfl_dt = false, double cfl = 0.0) {
+                double dt_fixed, hipStream_t s, double* speed, bool cfl_dt = false, double cfl = 0.0,
+                typename F::TS* sig_start = nullptr, typename F::TS** sig_end = nullptr) {
     using TD = typename F::TD;
     using TS = typename F::TS;
     TD* Ua = static_cast<TD*>(c->d_Ua);
     TD* Ub = static_cast<TD*>(c->d_Ub);
-    // Sigma ping-pongs between the caller's buffer and the scratch copy
-    // across the three stages; one copy at the end if it ends in scratch
-    TS* cur = sig;
-    TS* oth = static_cast<TS*>(c->d_sig2);
+    TS* cur = sig_start ? sig_start : sig;
+    TS* oth = cur == sig ? static_cast<TS*>(c->d_sig2) : sig;
     auto solve = [&](auto hasd, const typename F::TB* Us, const TD* Ds, double* spd = nullptr,
                      int* nspd = nullptr) -> int {
         TS* res = nullptr;
@@ -762,7 +766,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(fill_state_ghosts(c, Ub, s, true));
         IGR_TRY(solve(LaterD{}, U, Ub));
         IGR_TRY((flux_impl<F, MODE_STAGE3, true>(c, U, Ub, cur, nullptr, Unew, dtp, dt_fixed, s,
-                                                 c->viscous ? nullptr : speed, cur != sig ? sig : nullptr)));
+                                                 c->viscous ? nullptr : speed, !sig_end && cur != sig ? sig : nullptr)));
         if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3, true>(c, U, Ub, Unew, dtp, dt_fixed, s, speed)));
     } else {
         // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
@@ -778,9 +782,10 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         // with viscous terms their kernel, which completes the new state,
         // forms the CFL maxima instead of the flux kernel
         IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s,
-                                           c->viscous ? nullptr : speed, cur != sig ? sig : nullptr)));
+                                           c->viscous ? nullptr : speed, !sig_end && cur != sig ? sig : nullptr)));
         if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s, speed)));
     }
+    if (sig_end) *sig_end = cur;
     return IGR_OK;
 }
 
@@ -824,8 +829,12 @@ int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int n
     const bool use_cfl = !(dt_fixed > 0.0);
     const int nblk = int(c->viscous ? visc_blocks<F>(c) : flux_blocks<F>(c));
     TB* U = Ucaller;
+    // Sigma stays where a step's solve left it until the last step, which
+    // ends it in the caller's buffer
+    typename F::TS* scur = sig;
     for (int n = 0; n < nsteps; ++n) {
         TB* Unew = next_state<F>(c, U, Ucaller);
+        const bool last = n + 1 == nsteps;
         const double* dtp = nullptr;
         if (use_cfl) {
             if (n == 0) {
@@ -837,7 +846,8 @@ int advance_impl(igr_ctx* c, typename F::TB* Ucaller, typename F::TS* sig, int n
             }
             dtp = c->d_scalars;
         }
-        IGR_TRY(step_stages<F>(c, U, Unew, sig, dtp, dt_fixed, s, use_cfl && n + 1 < nsteps ? c->d_speed : nullptr));
+        IGR_TRY(step_stages<F>(c, U, Unew, sig, dtp, dt_fixed, s, use_cfl && !last ? c->d_speed : nullptr, false, 0.0,
+                               scur, last ? nullptr : &scur));
         U = Unew;
     }
     return settle_state<F>(c, U, Ucaller, s);
