@@ -204,10 +204,13 @@ int igr_step(igr_ctx *ctx, void *U, void *sigma, double cfl, double dt_fixed, do
  * by step n's last stage as it writes the new state (the same FP64
  * expression as the standalone reduction, on the values as stored; with
  * viscous terms by their kernel, which completes the new state), so the
- * separate pass over U runs only before the first step.  If dt_last is not
- * NULL the stream is synchronised, *dt_last
- * receives the last step's dt and the error flag is checked.
- * nsteps >= 0. */
+ * separate pass over U runs only before the first step.  Between steps
+ * Sigma may live in the context's scratch copy (a step starts from where
+ * the previous one's solve left it); sigma holds the last step's Sigma on
+ * return, as after nsteps igr_step calls (if a call fails part-way,
+ * sigma's contents are unspecified).  If dt_last is not NULL the stream
+ * is synchronised, *dt_last receives the last step's dt and the error
+ * flag is checked.  nsteps >= 0. */
 int igr_advance(igr_ctx *ctx, void *U, void *sigma, int32_t nsteps, double cfl, double dt_fixed, double *dt_last,
                 void *stream);
 
