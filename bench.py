@@ -66,13 +66,15 @@ FORM_BYTES = {"f64": (8, 8, 8, 8), "f32": (4, 4, 4, 4), "f16": (2, 2, 2, 4), "bf
 
 
 def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_block: int = 2,
-                               smoother: str = "jacobi") -> float:
+                               smoother: str = "jacobi", viscous: bool = False) -> float:
     """Compulsory HBM bytes per interior cell for one launch of `kernel`
     (averaged over the launches of one RK step).  The split form (bf16d)
     reads a later stage state as U^n (FP32) plus its BF16 difference,
     writes the differences of stages 1 and 2 and U^(n+1) (FP32) in stage 3,
     and its first Sigma pass stores 1/rho (FP32), which the later passes
-    read instead of rho."""
+    read instead of rho.  With the viscous terms a two-level first Sigma
+    pass (sigma_block 2 with an even Jacobi count, or red-black) also
+    writes the six stress components."""
     eu, ed, es, c = FORM_BYTES[precision]
     split = precision == "bf16d"
     if kernel == "flux_rk":
@@ -93,6 +95,8 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
         else:
             first = 5 * eu + eu + c
             later = 3 * eu + c
+        if viscous and nsweeps > 0 and sigma_block == 2 and (nsweeps % 2 == 0 or smoother == "rbgs"):
+            first += 6 * c
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":
         return 4 * eu + c          # rho, m read; b written
@@ -112,7 +116,8 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
     raise KeyError(kernel)
 
 
-def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int, smoother: str = "jacobi"):
+def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: int, smoother: str = "jacobi",
+                     viscous: bool = False):
     """Algorithmic GB/s and fraction of the 8 TB/s HBM peak of the flux and
     Sigma kernels (and, when they ran, the viscous stress and flux
     divergence) from their measured average launch time (sigma_block: the
@@ -123,7 +128,7 @@ def kernel_rooflines(kt, cells: int, precision: str, nsweeps: int, sigma_block: 
             continue
         ms, cnt = kt[k]
         if cnt:
-            ab = algorithmic_bytes_per_cell(k, precision, nsweeps, sigma_block, smoother) * cells
+            ab = algorithmic_bytes_per_cell(k, precision, nsweeps, sigma_block, smoother, viscous) * cells
             gbs = ab / (ms / cnt / 1e3) / 1e9
             out[k] = {"avg_ms": round(ms / cnt, 5), "launches": cnt, "achieved_GBs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -341,7 +346,7 @@ def jets_forms(n: int, forms, steps: int, warmup: int, err_steps: int, log=None,
         form = {"value": w.cells * steps / el, "ms_per_step": 1e3 * el / steps, "elapsed_s": el,
                 "device_bytes_in_use": total - free, "frac_of_288GB": round((total - free) / 288e9, 4),
                 "sigma_block": s.sigma_block, "kernel_times": kt}
-        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block, smoother))
+        form.update(kernel_rooflines(kt, w.cells, prec, w.nsweeps, s.sigma_block, smoother, mu > 0 or zeta > 0))
         if err_steps > 0:
             say(f"[bench] multi-jet {n}^3 {prec}: {err_steps} fixed-dt steps for the error")
             inputs.fill_multi_jet_state(w, s.interior(U))
@@ -448,12 +453,13 @@ def main():
         main_form = None
 
     value = cells * args.steps / el
+    visc = args.mu > 0 or args.zeta > 0
     # dominant kernel by total time in the timed region
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
     ms, count = kt[dom]
     avg_s = ms / count / 1e3
     try:
-        abytes = algorithmic_bytes_per_cell(dom, args.precision, w.nsweeps, sb, args.smoother) * cells
+        abytes = algorithmic_bytes_per_cell(dom, args.precision, w.nsweeps, sb, args.smoother, visc) * cells
     except KeyError:
         abytes = None
     achieved = abytes / avg_s / 1e9 if abytes else None
@@ -466,7 +472,7 @@ def main():
     kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1], "avg_ms": round(v[0] / v[1], 5)}
                for k, v in kt.items() if v[1] > 0}
     kernels.update({k + "_roofline": v for k, v in kernel_rooflines(kt, cells, args.precision, w.nsweeps,
-                                                                    sb, args.smoother).items()})
+                                                                    sb, args.smoother, visc).items()})
 
     forms = {}
     if args.workload == "multi_jet":
@@ -481,7 +487,7 @@ def main():
             e2, kt2, sb2 = run_form(w, f, args.steps, args.warmup, args.sigma_block, args.order, args.smoother)
             forms[f] = {"value": cells * args.steps / e2, "ms_per_step": 1e3 * e2 / args.steps,
                         "vs_f64": None, "sigma_block": sb2}
-            forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, sb2, args.smoother))
+            forms[f].update(kernel_rooflines(kt2, cells, f, w.nsweeps, sb2, args.smoother, visc))
             if args.precision == "f64":
                 forms[f]["vs_f64"] = round(forms[f]["value"] / value, 3)
 

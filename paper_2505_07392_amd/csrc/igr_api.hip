@@ -290,10 +290,11 @@ long long pair_speed_slots(const Geom& g) { return pair_shape(g, PAIR_NR_FIRST).
 
 // speed (FIRST, FP64 state without a difference; nullable): the pass also
 // leaves the CFL maxima of U there.  RB: one red-black sweep per pass
-// instead of two Jacobi sweeps.
+// instead of two Jacobi sweeps.  tau (FIRST; nullable): the pass also
+// stores the viscous stress of U there.
 template <class F, bool FIRST, bool HASD, bool RB = false>
 int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, const typename F::TS* Sin,
-              typename F::TS* Sout, hipStream_t s, double* speed = nullptr) {
+              typename F::TS* Sout, hipStream_t s, double* speed = nullptr, typename F::C* tau = nullptr) {
     using C = typename F::C;
     const Geom& g = c->g;
     // rows per block: the first pass that also forms the CFL maxima keeps
@@ -307,13 +308,28 @@ int pair_pass(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, cons
     C* ir = static_cast<C*>(c->d_ir);
     return launch(c, K_JACOBI, s, [&] {
         if (spd) {
-            if constexpr (SPD_OK)
-                k_sweep_pair<F, PAIR_NR_FIRST, true, false, true, RB>
-                    <<<dim3(unsigned(sh.blocks)), dim3(64, PAIR_NR_FIRST + 1), 0, s>>>(
+            if constexpr (SPD_OK) {
+                const dim3 grid(unsigned(sh.blocks)), block(64, PAIR_NR_FIRST + 1);
+                if (tau)
+                    k_sweep_pair<F, PAIR_NR_FIRST, true, false, true, RB, true><<<grid, block, 0, s>>>(
+                        U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag, tau, c->mu,
+                        c->zeta);
+                else
+                    k_sweep_pair<F, PAIR_NR_FIRST, true, false, true, RB><<<grid, block, 0, s>>>(
                         U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, speed, c->d_flag);
+            }
         } else {
-            k_sweep_pair<F, NR, FIRST, HASD, false, RB><<<dim3(unsigned(sh.blocks)), dim3(64, NR + 1), 0, s>>>(
-                U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y);
+            const dim3 grid(unsigned(sh.blocks)), block(64, NR + 1);
+            if constexpr (FIRST) {
+                if (tau) {
+                    k_sweep_pair<F, NR, true, HASD, false, RB, true><<<grid, block, 0, s>>>(
+                        U, D, Sin, Sout, b, ir, g, sh.zc, sh.tiles_x, sh.tiles_y, nullptr, nullptr, tau, c->mu,
+                        c->zeta);
+                    return;
+                }
+            }
+            k_sweep_pair<F, NR, FIRST, HASD, false, RB><<<grid, block, 0, s>>>(U, D, Sin, Sout, b, ir, g, sh.zc,
+                                                                             sh.tiles_x, sh.tiles_y);
         }
     });
 }
@@ -357,14 +373,18 @@ long long sweep_speed_slots(const Geom& g) { return sweep_shape(g, SWEEP_RY_FIRS
 // speed (FP64 contexts, nullable): if the solve starts with a single first
 // sweep, that sweep also leaves the CFL maxima of U there and *nspeed is
 // their count; otherwise *nspeed is 0.  The state swept from is U (+ D
-// with HASD: a split-form stage difference).
+// with HASD: a split-form stage difference).  tau (nullable): if the solve
+// starts with a two-level first pass, that pass also stores the viscous
+// stress of the state there and *tau_done is set; otherwise it is cleared.
 template <class F, bool HASD = false>
 int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, typename F::TS* in,
                     typename F::TS* other, int nsweeps, typename F::TS** result, hipStream_t s,
-                    double* speed = nullptr, int* nspeed = nullptr) {
+                    double* speed = nullptr, int* nspeed = nullptr, typename F::C* tau = nullptr,
+                    bool* tau_done = nullptr) {
     using C = typename F::C;
     using TS = typename F::TS;
     if (nspeed) *nspeed = 0;
+    if (tau_done) *tau_done = false;
     TS* src = in;
     TS* dst = other;
     auto swap = [&] {
@@ -406,8 +426,9 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
             for (int it = 0; it < nsweeps; ++it) {
                 if (it == 0) {
                     const bool spd = sizeof(C) == 8 && !HASD && speed != nullptr;
-                    IGR_TRY((pair_pass<F, true, HASD, true>(c, U, D, src, dst, s, spd ? speed : nullptr)));
+                    IGR_TRY((pair_pass<F, true, HASD, true>(c, U, D, src, dst, s, spd ? speed : nullptr, tau)));
                     if (spd && nspeed) *nspeed = int(pair_speed_slots(c->g));
+                    if (tau && tau_done) *tau_done = true;
                 } else {
                     IGR_TRY((pair_pass<F, false, HASD, true>(c, U, D, src, dst, s)));
                 }
@@ -437,8 +458,9 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
             // pairs + a single sweep)
             // FP64: the pass also forms the CFL maxima of U when asked
             const bool spd = sizeof(C) == 8 && !HASD && speed != nullptr;
-            IGR_TRY((pair_pass<F, true, HASD>(c, U, D, src, dst, s, spd ? speed : nullptr)));
+            IGR_TRY((pair_pass<F, true, HASD>(c, U, D, src, dst, s, spd ? speed : nullptr, tau)));
             if (spd && nspeed) *nspeed = int(pair_speed_slots(c->g));
+            if (tau && tau_done) *tau_done = true;
             swap();
             left -= 2;
         } else if (left > 0) {
@@ -642,7 +664,8 @@ long long visc_blocks(const igr_ctx* c) {
 // maxima of the new state there (visc_blocks values).
 template <class F, int MODE, bool HASD = false>
 int viscous_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, FluxOut<F, MODE>* out,
-                 const double* dtp, double dt_fixed, hipStream_t s, double* speed = nullptr) {
+                 const double* dtp, double dt_fixed, hipStream_t s, double* speed = nullptr,
+                 bool tau_ready = false) {
     {
         using C = typename F::C;
         constexpr int TY = visc_ty<C>();
@@ -653,10 +676,13 @@ int viscous_impl(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, F
         if (L.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the viscous launch");
         const FluxLaunch LS = flux_launch(g, IGR_STRESS_TY, IGR_STRESS_BLOCKS);
         if (LS.blocks() > 0x7fffffffLL) return fail(IGR_EINVAL, "grid too large for the stress launch");
-        IGR_TRY(launch(c, K_STRESS, s, [&] {
-            k_stress<F, IGR_STRESS_TY, HASD><<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
-                U, D, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
-        }));
+        // the stage's first Sigma pass may have stored the stress already
+        if (!tau_ready)
+            IGR_TRY(launch(c, K_STRESS, s, [&] {
+                k_stress<F, IGR_STRESS_TY, HASD>
+                    <<<dim3(unsigned(LS.blocks())), dim3(STRESS_TX, IGR_STRESS_TY), 0, s>>>(
+                        U, D, T6, g, c->mu, c->zeta, LS.tiles_x, LS.tiles_y, LS.zc);
+            }));
         for (int q = 0; q < 6; ++q) IGR_TRY(fill_sigma_ghosts(c, T6 + (size_t)q * g.fs, s));
         return launch(c, K_VISCOUS, s, [&] {
             const dim3 grid(unsigned(L.blocks())), block(VISC_TX, TY + 1);
@@ -723,10 +749,16 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
     TD* Ub = static_cast<TD*>(c->d_Ub);
     TS* cur = sig_start ? sig_start : sig;
     TS* oth = cur == sig ? static_cast<TS*>(c->d_sig2) : sig;
+    // with viscous terms the stage's first two-level Sigma pass also stores
+    // the stress of the stage input (tau: whether it did)
+    using C = typename F::C;
+    C* T6 = c->viscous ? static_cast<C*>(c->d_G) : nullptr;
+    bool tau = false;
     auto solve = [&](auto hasd, const typename F::TB* Us, const TD* Ds, double* spd = nullptr,
                      int* nspd = nullptr) -> int {
         TS* res = nullptr;
-        IGR_TRY((sigma_solve_buf<F, decltype(hasd)::value>(c, Us, Ds, cur, oth, c->nsweeps, &res, s, spd, nspd)));
+        IGR_TRY((sigma_solve_buf<F, decltype(hasd)::value>(c, Us, Ds, cur, oth, c->nsweeps, &res, s, spd, nspd, T6,
+                                                           &tau)));
         if (res != cur) {
             oth = cur;
             cur = res;
@@ -755,25 +787,25 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         IGR_TRY(solve(NoD{}, U, nullptr));
     }
     IGR_TRY((flux_impl<F, MODE_STAGE1>(c, U, nullptr, cur, nullptr, Ua, dtp, dt_fixed, s)));
-    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, nullptr, Ua, dtp, dt_fixed, s)));
+    if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE1>(c, U, nullptr, Ua, dtp, dt_fixed, s, nullptr, tau)));
     if constexpr (F::SPLIT) {
         // stage 2: U2 - Un = 1/4 ((U1 - Un) + dt L(U1)), U1 = Un + Ua
         IGR_TRY(fill_state_ghosts(c, Ua, s, true));
         IGR_TRY(solve(LaterD{}, U, Ua));
         IGR_TRY((flux_impl<F, MODE_STAGE2, true>(c, U, Ua, cur, nullptr, Ub, dtp, dt_fixed, s)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2, true>(c, U, Ua, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2, true>(c, U, Ua, Ub, dtp, dt_fixed, s, nullptr, tau)));
         // stage 3: Un+1 = Un + 2/3 ((U2 - Un) + dt L(U2)), U2 = Un + Ub
         IGR_TRY(fill_state_ghosts(c, Ub, s, true));
         IGR_TRY(solve(LaterD{}, U, Ub));
         IGR_TRY((flux_impl<F, MODE_STAGE3, true>(c, U, Ub, cur, nullptr, Unew, dtp, dt_fixed, s,
                                                  c->viscous ? nullptr : speed, !sig_end && cur != sig ? sig : nullptr)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3, true>(c, U, Ub, Unew, dtp, dt_fixed, s, speed)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3, true>(c, U, Ub, Unew, dtp, dt_fixed, s, speed, tau)));
     } else {
         // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
         IGR_TRY(fill_state_ghosts(c, Ua, s));
         IGR_TRY(solve(NoD{}, Ua, nullptr));
         IGR_TRY((flux_impl<F, MODE_STAGE2>(c, Ua, nullptr, cur, U, Ub, dtp, dt_fixed, s)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, nullptr, Ub, dtp, dt_fixed, s)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE2>(c, Ua, nullptr, Ub, dtp, dt_fixed, s, nullptr, tau)));
         // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place over Un; if the
         // solve ended in the scratch copy the kernel also writes Sigma's interior
         // into the caller's buffer (its ghosts are scratch)
@@ -783,7 +815,7 @@ int step_stages(igr_ctx* c, typename F::TB* U, typename F::TB* Unew, typename F:
         // forms the CFL maxima instead of the flux kernel
         IGR_TRY((flux_impl<F, MODE_STAGE3>(c, Ub, nullptr, cur, U, Unew, dtp, dt_fixed, s,
                                            c->viscous ? nullptr : speed, !sig_end && cur != sig ? sig : nullptr)));
-        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s, speed)));
+        if (c->viscous) IGR_TRY((viscous_impl<F, MODE_STAGE3>(c, Ub, nullptr, Unew, dtp, dt_fixed, s, speed, tau)));
     }
     if (sig_end) *sig_end = cur;
     return IGR_OK;

@@ -246,6 +246,12 @@ struct Geom {
     int periodic[3];
 };
 
+// index of the viscous stress component tau_ab (a <= b) among the six
+// stored ones: xx 0, xy 1, xz 2, yy 3, yz 4, zz 5
+__host__ __device__ constexpr int tau_index(int a, int b) {
+    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : tau_index(b, a);
+}
+
 __device__ __forceinline__ long long cell_offset(const Geom& g, int i, int j, int k) {
     return (long long)(k + G) * g.st[2] + (long long)(j + G) * g.st[1] + (i + G);
 }

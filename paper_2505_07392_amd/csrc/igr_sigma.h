@@ -648,6 +648,10 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
 // non-physical states raise *flag.
 // F: storage form; the state swept from is U (+ D with HASD, the split
 // form's stage difference).
+// TAU (FIRST): the pass also stores the viscous stress of eq. (5) formed
+// from the same velocity gradients, tau_ab = mu (G_ab + G_ba) +
+// (zeta - 2 mu / 3) tr(G) delta_ab, at the cells where it stores b (six
+// components, tau_index order; interior cells).
 // RB: one red-black Gauss-Seidel sweep instead of two Jacobi sweeps:
 // level 1 applies the update to the red cells ((i + j + k) even) and keeps
 // the black ones, level 2 applies it to the black cells from level 1's
@@ -659,7 +663,7 @@ struct PairIn<F, true> {    // first pass of a solve: the state instead of b and
 #ifndef IGR_SPLIT_FIRST_MINW
 #define IGR_SPLIT_FIRST_MINW 4
 #endif
-template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false, bool RB = false>
+template <class F, int NR, bool FIRST, bool HASD = false, bool SPD = false, bool RB = false, bool TAU = false>
 __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SPLIT_FIRST_MINW : 1) void k_sweep_pair(const typename F::TB* __restrict__ U,
                                                             const typename F::TD* __restrict__ D,
                                                             const typename F::TS* __restrict__ Sin,
@@ -668,8 +672,11 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                                                             typename F::C* __restrict__ irs, Geom g,
                                                             int zc, int tiles_x, int tiles_y,
                                                             double* __restrict__ speed = nullptr,
-                                                            int* __restrict__ flag = nullptr) {
+                                                            int* __restrict__ flag = nullptr,
+                                                            typename F::C* __restrict__ tau = nullptr,
+                                                            double mu_ = 0.0, double zeta_ = 0.0) {
     static_assert(!SPD || FIRST, "the CFL maxima need the first pass's state loads");
+    static_assert(!TAU || FIRST, "the stress needs the first pass's velocity gradients");
     using C = typename F::C;
     using SS = Storage<typename F::TS>;
     constexpr bool IRS = F::IRS;           // 1/rho stored by the first pass (split form)
@@ -894,6 +901,17 @@ __global__ __launch_bounds__(64 * (NR + 1), (F::SPLIT && FIRST && HASD) ? IGR_SP
                     // b and (split form) 1/rho, face-ghost layer included, for the later passes
                     const long long o = (long long)(z + G) * sz + (long long)(gy + G) * sy + (gx + G);
                     b[o] = bn;
+                    if constexpr (TAU) {
+                        const C mu = C(mu_), lam = C(zeta_) - C(2) * C(mu_) / C(3);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int e = a; e < 3; ++e) {
+                                C t = mu * (Gm[a][e] + Gm[e][a]);
+                                if (a == e) t += lam * tr;
+                                tau[(long long)tau_index(a, e) * fs + o] = t;
+                            }
+                    }
                     if constexpr (IRS) {
                         irs[o] = lir[a4][cy][cx];
                         if (gx == 0) irs[o - 1] = lir[a4][cy][cx - 1];

@@ -42,11 +42,6 @@
 
 namespace igr {
 
-// index of tau_ab (a <= b) among the six stored components
-__host__ __device__ constexpr int tau_index(int a, int b) {
-    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : tau_index(b, a);
-}
-
 // A block owns a 64 x TY tile of the x-y plane and marches a chunk of z
 // planes: rho and m of planes k-1, k, k+1 of its columns stay in a register
 // queue (plane k+2 is fetched one iteration ahead), plane k with a one-cell
