@@ -63,17 +63,36 @@ def test_viscous_rhs(vcase, order):
     assert err <= 1e-10
 
 
-def test_viscous_steps(vcase):
+# (smoother, sweeps, CFL time step): the case's odd count (the stress from
+# its own kernel), an even count (the first two-level Sigma pass forms it;
+# with a CFL step in FP64 that pass also forms the CFL maxima), red-black
+# passes (the same with one pass per sweep)
+STEP_MODES = {"jacobi_case": ("jacobi", None, False), "jacobi_4": ("jacobi", 4, False),
+              "jacobi_4_cfl": ("jacobi", 4, True), "rbgs_3": ("rbgs", 3, False)}
+
+
+@pytest.mark.parametrize("mode", sorted(STEP_MODES))
+def test_viscous_steps(vcase, mode):
     name, w = vcase
-    banner(f"viscous 3 steps {name}")
-    s = igr.Solver.from_workload(w)
+    smoother, nsweeps, cfl = STEP_MODES[mode]
+    ext = (w.nx, w.ny, w.nz)
+    if smoother == "rbgs" and any(w.faces[2 * d] == "periodic" and ext[d] % 2 for d in range(3)):
+        pytest.skip("red-black sweeps need even periodic extents")
+    banner(f"viscous 3 steps {name} {mode}")
+    s = igr.Solver.from_workload(w, nsweeps=nsweeps, smoother=smoother)
     U = s.state_from(w.U)
     sig = s.field_from(_sigma0(w))
-    prob = problem_from(w)
+    prob = problem_from(w, nsweeps=nsweeps)
+    prob.smoother = smoother
     Uo, so = torch.from_numpy(w.U.copy()), torch.from_numpy(_sigma0(w))
     dt = 0.5 * ref.compute_dt(prob, Uo, 0.5)
     for _ in range(3):
-        s.step(U, sig, dt_fixed=dt)
+        if cfl:
+            dt = ref.compute_dt(prob, Uo, 0.25)
+            dt_g = s.step(U, sig, cfl=0.25)
+            assert abs(dt_g - dt) <= 1e-14 * dt
+        else:
+            s.step(U, sig, dt_fixed=dt)
         Uo, so = ref.rk3_step(prob, Uo, so, dt)
     assert rel_linf(to_host(s, U), Uo.numpy()).max() <= TOL
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
@@ -122,8 +141,9 @@ def test_viscous_degenerate_extents(name):
     assert rel_linf(to_host(s, sig), so.numpy()).max() <= TOL
 
 
+@pytest.mark.parametrize("nsweeps", [None, 4])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16d"])
-def test_viscous_advance_with_cfl_matches_steps(prec):
+def test_viscous_advance_with_cfl_matches_steps(prec, nsweeps):
     """With viscosity igr_advance takes each later time step from the CFL
     maxima that the last stage's viscous kernel forms as it completes the
     new state; igr_step forms them from the state it starts from (FP64: in
@@ -132,8 +152,8 @@ def test_viscous_advance_with_cfl_matches_steps(prec):
     in case the compiler contracts it differently in the two kernels), so
     the states agree to a few units of the arithmetic."""
     w = _viscous(CASES["mixed_70x9x7"]())
-    banner(f"viscous advance vs steps ({prec})")
-    s = igr.Solver.from_workload(w, precision=prec)
+    banner(f"viscous advance vs steps ({prec}, sweeps {nsweeps})")
+    s = igr.Solver.from_workload(w, precision=prec, nsweeps=nsweeps)
     U1, U2 = s.state_from(w.U), s.state_from(w.U)
     S1, S2 = s.field_from(_sigma0(w)), s.field_from(_sigma0(w))
     dts = [s.step(U1, S1, cfl=0.4) for _ in range(3)]
