@@ -72,9 +72,9 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
     reads a later stage state as U^n (FP32) plus its BF16 difference,
     writes the differences of stages 1 and 2 and U^(n+1) (FP32) in stage 3,
     and its first Sigma pass stores 1/rho (FP32), which the later passes
-    read instead of rho.  With the viscous terms a two-level first Sigma
-    pass (sigma_block 2 with an even Jacobi count, or red-black) also
-    writes the six stress components."""
+    read instead of rho.  With the viscous terms the first Sigma pass (a
+    two-level pass or a single first sweep) also writes the six stress
+    components."""
     eu, ed, es, c = FORM_BYTES[precision]
     split = precision == "bf16d"
     if kernel == "flux_rk":
@@ -95,7 +95,7 @@ def algorithmic_bytes_per_cell(kernel: str, precision: str, nsweeps: int, sigma_
         else:
             first = 5 * eu + eu + c
             later = 3 * eu + c
-        if viscous and nsweeps > 0 and sigma_block == 2 and (nsweeps % 2 == 0 or smoother == "rbgs"):
+        if viscous and nsweeps > 0 and sigma_block in (1, 2):
             first += 6 * c
         return (nf * first + (npair + nsingle) * later) / (nf + npair + nsingle)
     if kernel == "source":

@@ -374,8 +374,9 @@ long long sweep_speed_slots(const Geom& g) { return sweep_shape(g, SWEEP_RY_FIRS
 // sweep, that sweep also leaves the CFL maxima of U there and *nspeed is
 // their count; otherwise *nspeed is 0.  The state swept from is U (+ D
 // with HASD: a split-form stage difference).  tau (nullable): if the solve
-// starts with a two-level first pass, that pass also stores the viscous
-// stress of the state there and *tau_done is set; otherwise it is cleared.
+// starts with a two-level first pass or a single first sweep, that pass
+// also stores the viscous stress of the state there and *tau_done is set;
+// otherwise (no sweeps, the fused march) it is cleared.
 template <class F, bool HASD = false>
 int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D, typename F::TS* in,
                     typename F::TS* other, int nsweeps, typename F::TS** result, hipStream_t s,
@@ -404,15 +405,26 @@ int sigma_solve_buf(igr_ctx* c, const typename F::TB* U, const typename F::TD* D
             constexpr bool SPD_OK = sizeof(C) == 8 && !HASD;   // CFL maxima formed in the first sweep: FP64
             const bool spd = SPD_OK && first && speed != nullptr;
             if (spd && nspeed) *nspeed = int(sf.blocks * SWEEP_RY_FIRST);
+            if (first && tau && tau_done) *tau_done = true;
             return launch(c, K_JACOBI, s, [&] {
+                const dim3 gf(unsigned(sf.blocks)), bf(64, SWEEP_RY_FIRST);
                 if (first && spd) {
-                    if constexpr (SPD_OK)
-                        k_sweep_z<F, true, SWEEP_RY_FIRST, true>
-                            <<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
+                    if constexpr (SPD_OK) {
+                        if (tau)
+                            k_sweep_z<F, true, SWEEP_RY_FIRST, true, false, true><<<gf, bf, 0, s>>>(
+                                U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, speed, c->d_flag, tau,
+                                c->mu, c->zeta);
+                        else
+                            k_sweep_z<F, true, SWEEP_RY_FIRST, true><<<gf, bf, 0, s>>>(
                                 U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, speed, c->d_flag);
+                    }
                 } else if (first) {
-                    k_sweep_z<F, true, SWEEP_RY_FIRST, false, HASD>
-                        <<<dim3(unsigned(sf.blocks)), dim3(64, SWEEP_RY_FIRST), 0, s>>>(
+                    if (tau)
+                        k_sweep_z<F, true, SWEEP_RY_FIRST, false, HASD, true><<<gf, bf, 0, s>>>(
+                            U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, nullptr, nullptr, tau,
+                            c->mu, c->zeta);
+                    else
+                        k_sweep_z<F, true, SWEEP_RY_FIRST, false, HASD><<<gf, bf, 0, s>>>(
                             U, D, src, out, b, ir, g, sf.zc, sf.tiles_x, sf.tiles_y, colour, nullptr, nullptr);
                 } else {
                     k_sweep_z<F, false, SWEEP_RY, false, HASD><<<dim3(unsigned(sl.blocks)), dim3(64, SWEEP_RY), 0, s>>>(

@@ -324,15 +324,20 @@ constexpr int SWEEP_RY_FIRST = IGR_SWEEP_RY_FIRST;   // rows of a first-sweep bl
 // wave leaves its maximum in speed[blockIdx.x * RY + wave] and non-physical
 // states raise *flag, so the time step of the stage needs no separate pass.
 // F: storage form; the state swept from is U (+ D with HASD, the split
-// form's stage difference).
-template <class F, bool FIRST, int RY, bool SPD = false, bool HASD = false>
+// form's stage difference).  TAU (FIRST): the sweep also stores the
+// viscous stress of eq. (5) formed from the source's velocity gradients
+// (six components, tau_index order) at every cell it stores b at.
+template <class F, bool FIRST, int RY, bool SPD = false, bool HASD = false, bool TAU = false>
 __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __restrict__ U,
                                                  const typename F::TD* __restrict__ D, const typename F::TS* Sin,
                                                  typename F::TS* Sout, typename F::C* __restrict__ b,
                                                  typename F::C* __restrict__ irs, Geom g, int zc,
                                                  int tiles_x, int tiles_y, int colour,
-                                                 double* __restrict__ speed, int* __restrict__ flag) {
+                                                 double* __restrict__ speed, int* __restrict__ flag,
+                                                 typename F::C* __restrict__ tau = nullptr, double mu_ = 0.0,
+                                                 double zeta_ = 0.0) {
     static_assert(!SPD || FIRST, "the CFL maxima need the first sweep's state loads");
+    static_assert(!TAU || FIRST, "the stress needs the first sweep's velocity gradients");
     using C = typename F::C;
     using SS = Storage<typename F::TS>;
     constexpr int PD = 3;   // own-column prefetch distance (planes)
@@ -491,6 +496,17 @@ __global__ __launch_bounds__(64 * RY) void k_sweep_z(const typename F::TB* __res
                 for (int d = 0; d < 3; ++d) tr2 += Gm[c][d] * Gm[d][c];
             bk = alpha * (tr2 + tr * tr);
             b[o] = bk;
+            if constexpr (TAU) {
+                const C mu = C(mu_), lam = C(zeta_) - C(2) * C(mu_) / C(3);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int e = a; e < 3; ++e) {
+                        C t = mu * (Gm[a][e] + Gm[e][a]);
+                        if (a == e) t += lam * tr;
+                        tau[(long long)tau_index(a, e) * g.fs + o] = t;
+                    }
+            }
         } else {
             bk = cc.b;
         }
